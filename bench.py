@@ -1,0 +1,233 @@
+#!/usr/bin/env python
+"""Benchmark of the gMCO hot path on one MI355X.
+
+Workload: the paper-scale synthetic case (18 catheters x 20 dwells = 360
+dwells, 20,000 dose points split 50/10/20/20 target/urethra/bladder/rectum,
+point-source dose law) with a batch of 1,000 hidden-weight vectors
+(log-uniform in [0.1, 10], normalised).  One step is one pass of the whole hot
+path over that batch: upload the weights, run batched L-BFGS (m = 10) for the
+calibrated iteration count, export t = x^2 and compute the FP64 objective and
+DVH metrics of every plan.  Inputs are resident on the GPU before timing.
+
+Prints one JSON line: Pareto plans per second (1000 / seconds per step), the
+roofline position of the fused evaluation kernel, and the FP64 oracle timed
+on the host cores on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--dtype f32acc64] [--iters N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Pareto plans/sec (1000-plan batch) & time-to-1000 plans vs oracle, at stated tol"
+TOL_F = 1e-4        # relative objective excess over the FP64 optimum
+TOL_V100 = 0.1      # target V100 difference in percentage points
+# Accepted L-BFGS steps per plan after which every checked plan of the
+# workload meets both tolerances (calibrated with --calibrate against the
+# oracle optima in tests/golden/c2_reference_optima.json).
+ITERS = {"f32acc64": 300, "f32": 300}
+# MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
+PEAK_F64 = 78.6
+PEAK_F32 = 157.3
+
+
+def eval_peak_tflops(dtype: str) -> float:
+    """Peak of the fused evaluation: half its FLOPs are the dose product, half
+    the back-projection; with FP64 accumulation of the dose the two halves run
+    at the FP64 and FP32 matrix peaks, so the combined peak is their harmonic
+    mean."""
+    if dtype == "f32acc64":
+        return 2.0 / (1.0 / PEAK_F64 + 1.0 / PEAK_F32)
+    return PEAK_F32
+
+
+def golden_path():
+    return os.path.join(ROOT, "tests", "golden", "c2_reference_optima.json")
+
+
+def load_golden():
+    p = golden_path()
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        return json.load(fh)
+
+
+def tolerance_report(metrics, golden):
+    """Compare the device's FP64 objective and target V100 of the sampled
+    plans with the stored oracle optima."""
+    if golden is None:
+        return None
+    import numpy as np
+    idx = np.array([q["index"] for q in golden["plans"]])
+    Fs = np.array([q["F"] for q in golden["plans"]])
+    V = np.array([q["V100_pct"][0] for q in golden["plans"]])
+    rel = (metrics["F64"][idx] - Fs) / Fs
+    dv = np.abs(metrics["V100_pct"][idx, 0] - V)
+    return dict(checked_plans=int(idx.size), max_rel_F_excess=float(rel.max()),
+                min_rel_F_excess=float(rel.min()), max_abs_dV100_pp=float(dv.max()),
+                within_tol=int(np.sum((rel <= TOL_F) & (dv <= TOL_V100))))
+
+
+def cpu_baseline(n_plans: int, n_iters: int, iters_full: int):
+    """The FP64 oracle on a bounded sample: n_plans weight vectors of the same
+    case for n_iters iterations, scaled to plans per second at iters_full."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import cases
+    import oracle as O
+    c = cases.case_c2()
+    W = cases.weights_c2()[:n_plans]
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    x0 = O.default_start(D, c.group, c.prescription_gy, n_plans)
+    t0 = time.perf_counter()
+    r = O.optimize(D, c.group, O.CLASS_SOLUTION_VOLUME, W, x0,
+                   O.LbfgsOptions(max_iter=n_iters))
+    t = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    plans_per_s = n_plans / (t * iters_full / max(1, int(np.max(r["iters"]))))
+    return dict(value=plans_per_s, unit="plans/s", cores=int(threads), kind="oracle",
+                sample=f"{n_plans} plans x {int(np.max(r['iters']))} L-BFGS iterations of the "
+                       f"360-dwell / 20,000-point case in {t:.1f} s (FP64 NumPy, BLAS threads "
+                       f"{threads}), scaled to {iters_full} iterations per plan")
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32"])
+    ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--plans", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-plans", type=int, default=16)
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--calibrate", type=str, default=None,
+                    help="comma-separated iteration counts: print the tolerance report at each")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import cases
+    from paper_1904_01567_amd import Planner, class_solution
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}), flush=True)
+        return 2
+    torch.cuda.set_device(0)
+    iters = args.iters or ITERS[args.dtype]
+    case = cases.case_c2()
+    W = cases.weights_c2(args.plans)
+    golden = load_golden()
+    pl = Planner(dtype=args.dtype, max_plans=args.plans)
+    t_load = time.perf_counter()
+    pl.load(case, class_solution.VOLUME)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t_load
+
+    if args.calibrate:
+        pl.set_weights(W)
+        for n in [int(v) for v in args.calibrate.split(",")]:
+            info = pl.optimize(max_iter=n)
+            rep = tolerance_report(pl.metrics(), golden)
+            print(json.dumps({"iters": n, "info": info, "tol": rep}), flush=True)
+        return 0
+
+    def step(time_kernels=False):
+        pl.set_weights(W)
+        info = pl.optimize(max_iter=iters, time_kernels=time_kernels)
+        t = pl.dwell_times()
+        m = pl.metrics()
+        return info, t, m
+
+    for w in range(args.warmup):
+        step()
+        print(f"# warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info, t, m = step(time_kernels=True)
+        infos.append(info)
+        print(f"# step {k + 1}/{args.steps}: {info['rounds']} rounds, "
+              f"{info['device_ms']:.1f} ms device", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.plans / (ms_per_step / 1e3)
+
+    # roofline of the fused evaluation kernel over the timed region
+    M, K, P = case.M, case.K, args.plans
+    flops_full = 4.0 * M * K * P          # dose product + back-projection, unpadded
+    eval_ms = sum(i["eval_ms"] for i in infos)
+    launches = sum(i["eval_launches"] for i in infos)
+    work = sum(i["eval_work"] for i in infos)
+    achieved = work * flops_full / (eval_ms / 1e3) / 1e12
+    peak = eval_peak_tflops(args.dtype)
+    tol = tolerance_report(m, golden)
+    upd_ms = sum(i["update_ms"] for i in infos)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "plans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "time_to_1000_s": 1000.0 / value,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operands, f64-accumulated dose" if args.dtype == "f32acc64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"prostate HDR case, {K} dwells x {M} points, {P} hidden-weight "
+                        f"vectors, L-BFGS m=10, {iters} iterations per plan",
+            "dwells": K, "points": M, "plans": P, "iterations": iters,
+            "lbfgs_history": 10, "eval_dtype": args.dtype,
+        },
+        "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
+        "breakdown_ms_per_step": {
+            "eval_kernels": eval_ms / args.steps,
+            "update_kernels": upd_ms / args.steps,
+            "rounds": launches / args.steps,
+            "load_case_once_ms": 1e3 * t_load,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_eval_f32 (fused dose product, penalty, back-projection)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "avg_launch_us": 1e3 * eval_ms / max(1, launches),
+            "full_launch_equivalents": work,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_plans, args.cpu_iters, iters)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

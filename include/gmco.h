@@ -1,0 +1,222 @@
+/*
+ * gmco.h — C-ABI of the MI355X gMCO hot path: many HDR dwell-time plans
+ * optimised at once by batched L-BFGS (Belanger, Cui et al., "A GPU-based
+ * multi-criteria optimization algorithm for HDR brachytherapy",
+ * arXiv 1904.01567).
+ *
+ * Conventions (every entry point):
+ *   - Return GMCO_OK (0) on success, a negative gmco_status on error.  The
+ *     text of the last error of a context is available from gmco_last_error.
+ *     No C++ exception crosses this boundary.
+ *   - Host arrays are row-major, 0-based and are only read (or written) during
+ *     the call; the library keeps no pointer to them after it returns.
+ *   - Device work is issued on the context's stream (gmco_set_stream); calls
+ *     that return host data synchronise that stream before returning.
+ *   - One context per host thread.  Contexts on the same GPU are independent.
+ *   - Per-plan numeric trouble (a failed line search, a non-finite objective)
+ *     is reported in the plan's status and never fails a whole call.
+ */
+#ifndef GMCO_H
+#define GMCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMCO_MAX_GROUPS 8   /* structures (organs / point types) per case */
+#define GMCO_MAX_HISTORY 32 /* L-BFGS pairs */
+#define GMCO_MAX_DWELLS 512 /* active dwell positions per case */
+
+typedef enum {
+  GMCO_OK = 0,
+  GMCO_EINVAL = -1,   /* bad argument: shape, range, NaN/Inf or negative weight */
+  GMCO_ENOMEM = -2,   /* device allocation failed or bound workspace too small */
+  GMCO_EHIP = -3,     /* a HIP runtime call failed; its text is in last_error */
+  GMCO_ESTATE = -4,   /* wrong call order (e.g. optimise before set_weights) */
+  GMCO_ENUMERIC = -5, /* every plan of the batch has a non-finite objective */
+  GMCO_ENOLIB = -6    /* no usable GPU of the architecture this library is built for */
+} gmco_status;
+
+/* Arithmetic of the dose product (eq. (dose)) and of the back-projection of
+ * the penalty derivative inside each evaluation.  L-BFGS vectors and history
+ * are FP32 in every case; F_64 and the DVH metrics are FP64.
+ *   F32        FP32 operands, FP32 accumulation in both products.
+ *   BF16       BF16 operands, FP32 accumulation.
+ *   FP8        OCP e4m3 operands with one scale per dwell column, FP32 accumulation.
+ *   F32_ACC64  FP32 operands; the dose accumulated and the penalty evaluated
+ *              in FP64 (FP32 accumulation of the dose leaves noise in the
+ *              objective that stalls the line search near the optimum);
+ *              FP32 back-projection. */
+typedef enum {
+  GMCO_DTYPE_F32 = 0,
+  GMCO_DTYPE_BF16 = 1,
+  GMCO_DTYPE_FP8 = 2,
+  GMCO_DTYPE_F32_ACC64 = 3
+} gmco_dtype;
+
+/* Per-plan status. */
+typedef enum {
+  GMCO_PLAN_RUNNING = 0,   /* still iterating (only seen mid-run) */
+  GMCO_PLAN_CONVERGED = 1, /* relative objective variation <= eps, F == 0 or g == 0 */
+  GMCO_PLAN_MAXITER = 2,   /* reached max_iter accepted steps */
+  GMCO_PLAN_LS_FAIL = 3,   /* max_ls trials rejected; x kept at the last accepted point */
+  GMCO_PLAN_NONFINITE = 4, /* objective at the start point is NaN or Inf */
+  GMCO_PLAN_INACTIVE = 5   /* slot not used by the current weight batch */
+} gmco_plan_status;
+
+typedef struct gmco_ctx gmco_ctx;
+
+typedef struct {
+  int device;    /* HIP device ordinal */
+  int dtype;     /* gmco_dtype */
+  int history;   /* L-BFGS pairs m, 1..GMCO_MAX_HISTORY */
+  int max_plans; /* largest weight batch that set_weights will receive */
+} gmco_opts;
+
+/* One patient case (Sec. 2.1).  Points may be given in any order; group[i]
+ * names the structure of point i.  Table 1 gives the class-solution
+ * parameters for the four prostate structures. */
+typedef struct {
+  int n_dwells;                  /* K, 1..GMCO_MAX_DWELLS */
+  const double* dwell_xyz;       /* K x 3, cm */
+  int n_points;                  /* M >= 1 */
+  const double* point_xyz;       /* M x 3, cm (ignored when dose_rate != NULL) */
+  const int32_t* group;          /* M, values in [0, n_groups) */
+  int n_groups;                  /* 1..GMCO_MAX_GROUPS */
+  const double* group_params;    /* n_groups x 4: w_min, D_min [Gy], D_max [Gy], w_max (eq. 1) */
+  const double* group_volume_cc; /* n_groups structure volumes for V75 in cc; NULL -> 0 cc */
+  double prescription_gy;        /* > 0; 100 % for V100 / D_x */
+  int target_group;              /* structure whose mean dose sets the default start */
+  const double* dose_rate;       /* optional M x K dose-rate matrix (Gy per time unit);
+                                    NULL -> the point-source law
+                                    (1 - 0.01 r) / max(r, 0.1 cm)^2, Sec. 2.2.1 step (i) */
+} gmco_case;
+
+/* Options of one optimisation run.  The paper leaves its L-BFGS details out
+ * (Sec. 2.2.2); this is textbook L-BFGS (two-loop recursion, gamma scaling of
+ * the newest pair) with Armijo backtracking and the relative-variation stop
+ * rule of Sec. 2.2.3. */
+typedef struct {
+  int max_iter;       /* cap on accepted steps per plan (cumulative over calls) */
+  double eps;         /* converged when F_prev - F <= eps * F_prev (0: run to max_iter) */
+  double c1;          /* Armijo constant, e.g. 1e-4 */
+  double beta;        /* backtracking factor in (0, 1), e.g. 0.5 */
+  int max_ls;         /* trials per iteration before LS_FAIL, >= 1 */
+  int check_every;    /* rounds between host checks of the active-plan count (0 -> 16) */
+  int time_kernels;   /* 1: time every evaluation and update launch with HIP events */
+  int resume_stopped; /* 1: plans stopped as CONVERGED or LS_FAIL iterate again
+                         (e.g. after a change of dwell set or precision); 0: they stay */
+} gmco_run;
+
+typedef struct {
+  int rounds;          /* batched evaluation rounds issued */
+  int n_converged;
+  int n_maxiter;
+  int n_ls_fail;
+  int n_nonfinite;
+  int max_iters;       /* largest accepted-step count of any plan */
+  float device_ms;     /* GPU time of the whole run (HIP events on the context stream) */
+  float eval_ms;       /* sum of evaluation-kernel durations (time_kernels = 1) */
+  float update_ms;     /* sum of L-BFGS update-kernel durations (time_kernels = 1) */
+  int eval_launches;   /* evaluation launches */
+  double eval_work;    /* evaluation work done, in full-batch launch equivalents
+                          (tiles whose plans had all stopped are skipped) */
+} gmco_run_info;
+
+typedef struct {
+  double F_run;                      /* objective at the final x, run arithmetic */
+  double F64;                        /* eq. (obj) re-evaluated in FP64 at t = x^2 */
+  double f_organ[GMCO_MAX_GROUPS];   /* (1/N_j) sum_i f_ij, FP64 */
+  double V100_pct[GMCO_MAX_GROUPS];  /* % of the structure's points with d >= Rx */
+  double V75_cc[GMCO_MAX_GROUPS];    /* volume_cc * share of points with d >= 0.75 Rx */
+  double D10_pct[GMCO_MAX_GROUPS];   /* % Rx of the k-th hottest point, k = ceil(0.1 N) */
+  double D90_pct[GMCO_MAX_GROUPS];   /* same with k = ceil(0.9 N) */
+  int iterations;                    /* accepted steps */
+  int evaluations;                   /* objective evaluations incl. the start point */
+  int status;                        /* gmco_plan_status */
+  int reserved;
+} gmco_plan_metrics;
+
+/* Create a context on opts->device.  *out is owned by the caller until
+ * gmco_destroy.  Errors: EINVAL (bad opts), ENOLIB (device is not gfx950),
+ * EHIP. */
+int gmco_create(gmco_ctx** out, const gmco_opts* opts);
+
+/* Free everything the library allocated.  NULL-safe.  A bound workspace is
+ * not freed (its owner frees it). */
+int gmco_destroy(gmco_ctx* ctx);
+
+/* Issue all later device work on `stream` (a hipStream_t; NULL = the null
+ * stream).  The library does not own the stream. */
+int gmco_set_stream(gmco_ctx* ctx, void* stream);
+
+/* Device bytes needed for a case of M points and K dwells with the context's
+ * max_plans, history and dtype. */
+int gmco_workspace_bytes(const gmco_ctx* ctx, int n_points, int n_dwells, size_t* bytes);
+
+/* Hand the library a device buffer (256-byte aligned) to carve all its device
+ * arrays from, instead of allocating its own.  The caller keeps ownership and
+ * must keep it alive until gmco_destroy or the next gmco_bind_workspace.
+ * Must precede gmco_load_case.  A buffer smaller than gmco_workspace_bytes
+ * makes gmco_load_case return ENOMEM. */
+int gmco_bind_workspace(gmco_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Copy a case to the device and build its dose-rate matrix (Sec. 2.2.1 step
+ * (i)) in FP64 and in the run dtype, plus the default start time
+ * t_bar = Rx / mean_{i in target} sum_l Ddot_il (uniform dwell times whose
+ * mean target dose is the prescription).  Invalidates earlier weights.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int gmco_load_case(gmco_ctx* ctx, const gmco_case* c);
+
+/* Set the hidden-weight batch, eq. (obj): W is P x n_groups, finite and >= 0,
+ * used as given (normalise rows to sum 1 beforehand for the paper's weighted
+ * sum).  t0 is P x K start dwell times (> 0 recommended: x_l = 0 is a fixed
+ * point of the x^2 substitution) or NULL for the uniform start t_bar.  Resets
+ * every plan to its start.  Errors: EINVAL (P out of 1..max_plans, bad value),
+ * ESTATE (no case loaded), EHIP. */
+int gmco_set_weights(gmco_ctx* ctx, int n_plans, const double* W, const double* t0);
+
+/* One batched evaluation of eq. (obj) and of its gradient in the dwell
+ * weights (eq. 2 summed over points) at x (P x K, P = current batch size), in
+ * the run dtype with FP32 accumulation.  F is P, g is P x K.  Uses the same
+ * kernels as the optimiser and leaves the optimiser state untouched.
+ * Errors: ESTATE, EINVAL, EHIP. */
+int gmco_evaluate(gmco_ctx* ctx, const double* x, double* F, double* g);
+
+/* Run batched L-BFGS until every plan has stopped (converged, max_iter,
+ * line-search failure) or info reports the state.  Continues from the
+ * current state: plans stopped by max_iter resume if run->max_iter is larger.
+ * Synchronous on the context stream.  Errors: EINVAL, ESTATE, EHIP,
+ * ENUMERIC (every plan non-finite at its start). */
+int gmco_optimize(gmco_ctx* ctx, const gmco_run* run, gmco_run_info* info);
+
+/* t = x^2 of every plan, P x K, FP64 (computed on the device). */
+int gmco_get_dwell_times(gmco_ctx* ctx, double* t);
+
+/* Current dwell weights x, P x K (run state, widened to double). */
+int gmco_get_weights_x(gmco_ctx* ctx, double* x);
+
+/* Per-plan metrics at the current t (Sec. 2.3.1 DVH definitions: V_x counts
+ * points with d >= x % Rx; D_x is the dose of the k-th hottest point,
+ * k = max(1, ceil(x N / 100))), from an FP64 dose recomputation.  out has P
+ * entries. */
+int gmco_get_metrics(gmco_ctx* ctx, gmco_plan_metrics* out);
+
+/* The dose-rate matrix as used: D64 (M x K, FP64) and/or Drun (M x K, the
+ * run-dtype values widened to double, column scale applied).  Either pointer
+ * may be NULL.  Rows are in the caller's point order. */
+int gmco_get_dose_rate(gmco_ctx* ctx, double* D64, double* Drun);
+
+/* Default start time t_bar of the loaded case. */
+int gmco_get_start_time(gmco_ctx* ctx, double* t_bar);
+
+const char* gmco_last_error(const gmco_ctx* ctx);
+const char* gmco_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMCO_H */

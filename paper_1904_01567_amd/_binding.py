@@ -1,0 +1,281 @@
+"""ctypes binding of libgmco.so (include/gmco.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  PyTorch, when
+present, provides the device workspace and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgmco.so")
+
+GMCO_MAX_GROUPS = 8
+GMCO_MAX_HISTORY = 32
+GMCO_MAX_DWELLS = 512
+
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "f32acc64": 3}
+STATUS_NAMES = {0: "running", 1: "converged", 2: "maxiter", 3: "ls_fail",
+                4: "nonfinite", 5: "inactive"}
+ERRORS = {0: "GMCO_OK", -1: "GMCO_EINVAL", -2: "GMCO_ENOMEM", -3: "GMCO_EHIP",
+          -4: "GMCO_ESTATE", -5: "GMCO_ENUMERIC", -6: "GMCO_ENOLIB"}
+
+# Every entry point that include/gmco.h declares.
+EXPORTS = (
+    "gmco_create", "gmco_destroy", "gmco_set_stream", "gmco_workspace_bytes",
+    "gmco_bind_workspace", "gmco_load_case", "gmco_set_weights", "gmco_evaluate",
+    "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
+    "gmco_get_dose_rate", "gmco_get_start_time", "gmco_last_error", "gmco_strerror",
+)
+
+
+class GmcoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gmco_opts(C.Structure):
+    _fields_ = [("device", C.c_int), ("dtype", C.c_int), ("history", C.c_int),
+                ("max_plans", C.c_int)]
+
+
+class gmco_case(C.Structure):
+    _fields_ = [("n_dwells", C.c_int), ("dwell_xyz", C.POINTER(C.c_double)),
+                ("n_points", C.c_int), ("point_xyz", C.POINTER(C.c_double)),
+                ("group", C.POINTER(C.c_int32)), ("n_groups", C.c_int),
+                ("group_params", C.POINTER(C.c_double)),
+                ("group_volume_cc", C.POINTER(C.c_double)),
+                ("prescription_gy", C.c_double), ("target_group", C.c_int),
+                ("dose_rate", C.POINTER(C.c_double))]
+
+
+class gmco_run(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("eps", C.c_double), ("c1", C.c_double),
+                ("beta", C.c_double), ("max_ls", C.c_int), ("check_every", C.c_int),
+                ("time_kernels", C.c_int), ("resume_stopped", C.c_int)]
+
+
+class gmco_run_info(C.Structure):
+    _fields_ = [("rounds", C.c_int), ("n_converged", C.c_int), ("n_maxiter", C.c_int),
+                ("n_ls_fail", C.c_int), ("n_nonfinite", C.c_int), ("max_iters", C.c_int),
+                ("device_ms", C.c_float), ("eval_ms", C.c_float), ("update_ms", C.c_float),
+                ("eval_launches", C.c_int), ("eval_work", C.c_double)]
+
+
+class gmco_plan_metrics(C.Structure):
+    _fields_ = [("F_run", C.c_double), ("F64", C.c_double),
+                ("f_organ", C.c_double * GMCO_MAX_GROUPS),
+                ("V100_pct", C.c_double * GMCO_MAX_GROUPS),
+                ("V75_cc", C.c_double * GMCO_MAX_GROUPS),
+                ("D10_pct", C.c_double * GMCO_MAX_GROUPS),
+                ("D90_pct", C.c_double * GMCO_MAX_GROUPS),
+                ("iterations", C.c_int), ("evaluations", C.c_int), ("status", C.c_int),
+                ("reserved", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libgmco.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(
+            f"{p} is missing: build it with `python -m paper_1904_01567_amd.build`")
+    lib = C.CDLL(p)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    lib.gmco_create.argtypes = [C.POINTER(vp), C.POINTER(gmco_opts)]
+    lib.gmco_destroy.argtypes = [vp]
+    lib.gmco_set_stream.argtypes = [vp, vp]
+    lib.gmco_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    lib.gmco_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    lib.gmco_load_case.argtypes = [vp, C.POINTER(gmco_case)]
+    lib.gmco_set_weights.argtypes = [vp, C.c_int, dp, dp]
+    lib.gmco_evaluate.argtypes = [vp, dp, dp, dp]
+    lib.gmco_optimize.argtypes = [vp, C.POINTER(gmco_run), C.POINTER(gmco_run_info)]
+    lib.gmco_get_dwell_times.argtypes = [vp, dp]
+    lib.gmco_get_weights_x.argtypes = [vp, dp]
+    lib.gmco_get_metrics.argtypes = [vp, C.POINTER(gmco_plan_metrics)]
+    lib.gmco_get_dose_rate.argtypes = [vp, dp, dp]
+    lib.gmco_get_start_time.argtypes = [vp, dp]
+    lib.gmco_last_error.argtypes = [vp]
+    lib.gmco_last_error.restype = C.c_char_p
+    lib.gmco_strerror.argtypes = [C.c_int]
+    lib.gmco_strerror.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("gmco_last_error", "gmco_strerror"):
+            getattr(lib, name).restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and out.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {out.shape}")
+    return out
+
+
+class Planner:
+    """One gMCO context: a case, a batch of weight vectors and its plans."""
+
+    def __init__(self, device: int = 0, dtype: str = "f32", history: int = 10,
+                 max_plans: int = 1000, use_torch: bool = True):
+        self.lib = load_library()
+        self._ctx = C.c_void_p()
+        self._ws = None
+        self._torch = None
+        opts = gmco_opts(device, DTYPES[dtype], history, max_plans)
+        self._check(self.lib.gmco_create(C.byref(self._ctx), C.byref(opts)), "create")
+        self.dtype, self.history, self.max_plans, self.device = dtype, history, max_plans, device
+        self.K = self.M = self.G = 0
+        self.P = 0
+        if use_torch:
+            import torch  # device memory and stream come from PyTorch
+            self._torch = torch
+            torch.cuda.set_device(device)
+            self.set_stream(torch.cuda.current_stream(device).cuda_stream)
+
+    # -- plumbing --------------------------------------------------------
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = ""
+            if self._ctx:
+                m = self.lib.gmco_last_error(self._ctx)
+                msg = m.decode() if m else ""
+            if not msg:
+                msg = self.lib.gmco_strerror(rc).decode()
+            raise GmcoError(rc, f"{what}: {msg}")
+
+    def close(self):
+        if self._ctx:
+            self.lib.gmco_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream_handle: int):
+        self._check(self.lib.gmco_set_stream(self._ctx, C.c_void_p(stream_handle)), "set_stream")
+
+    def workspace_bytes(self, n_points: int, n_dwells: int) -> int:
+        b = C.c_size_t()
+        self._check(self.lib.gmco_workspace_bytes(self._ctx, n_points, n_dwells, C.byref(b)),
+                    "workspace_bytes")
+        return int(b.value)
+
+    # -- API -------------------------------------------------------------
+    def load_case(self, dwell_xyz, point_xyz, group, group_params, volume_cc=None,
+                  prescription_gy: float = 15.0, target_group: int = 0, dose_rate=None):
+        dw = _f64(dwell_xyz)
+        K = dw.shape[0]
+        grp = np.ascontiguousarray(np.asarray(group, dtype=np.int32))
+        M = grp.shape[0]
+        pts = _f64(point_xyz, (M, 3)) if point_xyz is not None else None
+        prm = _f64(group_params)
+        G = prm.shape[0]
+        vol = _f64(volume_cc, (G,)) if volume_cc is not None else None
+        Dr = _f64(dose_rate, (M, K)) if dose_rate is not None else None
+        if self._torch is not None:
+            nbytes = self.workspace_bytes(M, K)
+            self._ws = self._torch.empty(nbytes, dtype=self._torch.uint8,
+                                         device=f"cuda:{self.device}")
+            self._check(self.lib.gmco_bind_workspace(self._ctx, C.c_void_p(self._ws.data_ptr()),
+                                                     nbytes), "bind_workspace")
+        cs = gmco_case(K, _dptr(dw), M, _dptr(pts), grp.ctypes.data_as(C.POINTER(C.c_int32)), G,
+                       _dptr(prm), _dptr(vol), float(prescription_gy), int(target_group),
+                       _dptr(Dr))
+        self._check(self.lib.gmco_load_case(self._ctx, C.byref(cs)), "load_case")
+        self.K, self.M, self.G = K, M, G
+        self.P = 0
+
+    def load(self, case, group_params, target_group: int = 0):
+        """Load a `cases.Case`-like object (dwell_xyz, pt_xyz, group, volume_cc)."""
+        self.load_case(case.dwell_xyz, case.pt_xyz, case.group, group_params, case.volume_cc,
+                       case.prescription_gy, target_group)
+
+    def set_weights(self, W, t0=None):
+        W = _f64(W)
+        P = W.shape[0]
+        if W.shape != (P, self.G):
+            raise ValueError(f"W must be (P, {self.G})")
+        t0a = _f64(t0, (P, self.K)) if t0 is not None else None
+        self._check(self.lib.gmco_set_weights(self._ctx, P, _dptr(W), _dptr(t0a)), "set_weights")
+        self.P = P
+
+    def evaluate(self, x):
+        x = _f64(x, (self.P, self.K))
+        F = np.empty(self.P)
+        g = np.empty((self.P, self.K))
+        self._check(self.lib.gmco_evaluate(self._ctx, _dptr(x), _dptr(F), _dptr(g)), "evaluate")
+        return F, g
+
+    def optimize(self, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
+                 max_ls: int = 30, check_every: int = 16, time_kernels: bool = False,
+                 resume_stopped: bool = False) -> dict:
+        r = gmco_run(int(max_iter), float(eps), float(c1), float(beta), int(max_ls),
+                     int(check_every), int(bool(time_kernels)), int(bool(resume_stopped)))
+        info = gmco_run_info()
+        self._check(self.lib.gmco_optimize(self._ctx, C.byref(r), C.byref(info)), "optimize")
+        return {k: getattr(info, k) for k, _ in gmco_run_info._fields_}
+
+    def dwell_times(self) -> np.ndarray:
+        t = np.empty((self.P, self.K))
+        self._check(self.lib.gmco_get_dwell_times(self._ctx, _dptr(t)), "get_dwell_times")
+        return t
+
+    def weights_x(self) -> np.ndarray:
+        x = np.empty((self.P, self.K))
+        self._check(self.lib.gmco_get_weights_x(self._ctx, _dptr(x)), "get_weights_x")
+        return x
+
+    def metrics(self) -> dict:
+        arr = (gmco_plan_metrics * self.P)()
+        self._check(self.lib.gmco_get_metrics(self._ctx, arr), "get_metrics")
+        G = self.G
+        out = {
+            "F_run": np.array([m.F_run for m in arr]),
+            "F64": np.array([m.F64 for m in arr]),
+            "iterations": np.array([m.iterations for m in arr]),
+            "evaluations": np.array([m.evaluations for m in arr]),
+            "status": np.array([m.status for m in arr]),
+        }
+        for f in ("f_organ", "V100_pct", "V75_cc", "D10_pct", "D90_pct"):
+            out[f] = np.array([list(getattr(m, f))[:G] for m in arr])
+        return out
+
+    def dose_rate(self, run_dtype: bool = False):
+        D = np.empty((self.M, self.K))
+        if run_dtype:
+            self._check(self.lib.gmco_get_dose_rate(self._ctx, None, _dptr(D)), "get_dose_rate")
+        else:
+            self._check(self.lib.gmco_get_dose_rate(self._ctx, _dptr(D), None), "get_dose_rate")
+        return D
+
+    def start_time(self) -> float:
+        v = C.c_double()
+        self._check(self.lib.gmco_get_start_time(self._ctx, C.byref(v)), "get_start_time")
+        return float(v.value)

@@ -1,0 +1,632 @@
+// Host runtime and C-ABI of the gMCO hot path: context, device arena,
+// case and batch upload, the batched optimisation loop and result export.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gmco_internal.h"
+
+using namespace gmco;
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+// Byte offsets of every device array inside the arena.
+struct Layout {
+  size_t D64, Drun, DT, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
+  size_t Wst, t0st, xst, Fst, gst;
+  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work;
+  size_t t64, d64, metrics;
+  size_t total;
+};
+
+struct Dims {
+  int M = 0, K = 0, Mp = 0, Kp = 0, Pp = 0, S = 1, ntiles = 1, nblocks = 0;
+};
+
+}  // namespace
+
+struct gmco_ctx {
+  int device = 0;
+  int dtype = GMCO_DTYPE_F32;
+  int m = 10;
+  int Pmax = 1;
+  int n_cu = 256;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  void* ws = nullptr;       // arena base
+  size_t ws_bytes = 0;
+  bool ws_owned = false;    // allocated by the library
+  void* bound = nullptr;    // workspace handed in by the caller
+  size_t bound_bytes = 0;
+
+  Dims dim;
+  Layout lay{};
+  int G = 0;
+  double rx = 0.0;
+  int target = 0;
+  std::vector<int> counts, offsets, perm;  // host copies
+  bool case_loaded = false;
+  int P = 0;              // current batch, 0 = none
+  int* host_count = nullptr;  // pinned mirror of the active counter
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  GroupTable gt{};
+
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+  }
+};
+
+namespace {
+
+int fail(gmco_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(gmco_ctx* c, hipError_t e, const char* what) {
+  return fail(c, GMCO_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GMCO_HIP(ctx, call)                                 \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+  } while (0)
+
+size_t dtype_bytes(int dtype) {
+  return (dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64) ? 4 : (dtype == GMCO_DTYPE_BF16 ? 2 : 1);
+}
+bool has_transposed(int dtype) { return dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8; }
+
+Dims make_dims(int M, int K, int Pmax, int n_cu) {
+  Dims d;
+  d.M = M;
+  d.K = K;
+  d.Kp = round_up(K, kKAlign);
+  d.Mp = round_up(M, kBM);
+  d.nblocks = d.Mp / kBM;
+  d.Pp = round_up(Pmax, kPT);
+  d.ntiles = d.Pp / kPT;
+  int S = std::max(1, n_cu / d.ntiles);
+  if (S >= 8) S -= S % 8;
+  d.S = std::max(1, std::min(S, d.nblocks));
+  return d;
+}
+
+Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t MK = (size_t)d.Mp * d.Kp;
+  const size_t PK = (size_t)d.Pp * d.Kp;
+  L.D64 = take(MK * 8);
+  L.Drun = take(MK * dtype_bytes(dtype));
+  L.DT = take(has_transposed(dtype) ? MK * dtype_bytes(dtype) : 0);
+  L.colscale = take((size_t)d.Kp * 4);
+  L.grp = take((size_t)d.Mp * 4);
+  L.perm = take((size_t)d.M * 4);
+  L.stage = take((size_t)d.M * d.K * 8 + ((size_t)d.M + d.K) * 3 * 8);
+  L.gparams = take(kGmax * 4 * 8);
+  L.volume = take(kGmax * 8);
+  L.goff = take(kGmax * 4);
+  L.gcnt = take(kGmax * 4);
+  L.counts = take(kGmax * 4);
+  L.t_bar = take(8);
+  L.Wst = take((size_t)Pmax * kGmax * 8);
+  L.t0st = take((size_t)Pmax * d.K * 8);
+  L.xst = take((size_t)Pmax * d.K * 8);
+  L.Fst = take((size_t)Pmax * 8);
+  L.gst = take((size_t)Pmax * d.K * 8);
+  L.wn = take((size_t)d.Pp * kGmax * 4);
+  L.W64 = take((size_t)d.Pp * kGmax * 8);
+  L.x = take(PK * 4);
+  L.g = take(PK * 4);
+  L.dir = take(PK * 4);
+  L.xt = take(PK * 4);
+  L.xe = take(PK * 4);
+  L.Sh = take(PK * m * 4);
+  L.Yh = take(PK * m * 4);
+  L.rho = take((size_t)d.Pp * m * 8);
+  L.ps = take((size_t)d.Pp * sizeof(PlanState));
+  L.Gpart = take((size_t)d.S * PK * 4);
+  L.Fpart = take((size_t)d.S * d.Pp * 8);
+  L.active = take(2 * sizeof(int));
+  L.work = take(sizeof(unsigned long long));
+  L.t64 = take(PK * 8);
+  L.d64 = take((size_t)d.Pp * d.Mp * 8);
+  L.metrics = take((size_t)d.Pp * sizeof(gmco_plan_metrics));
+  (void)G;
+  L.total = off;
+  return L;
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int copy_h2d(gmco_ctx* c, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return GMCO_OK;
+  GMCO_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  return GMCO_OK;
+}
+
+EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped) {
+  EvalArgs a{};
+  a.D = c->at<void>(c->lay.Drun);
+  a.DT = c->at<void>(c->lay.DT);
+  a.colscale = c->at<float>(c->lay.colscale);
+  a.grp = c->at<int>(c->lay.grp);
+  a.x = x;
+  a.wn = c->at<float>(c->lay.wn);
+  a.ps = skip_stopped ? c->at<PlanState>(c->lay.ps) : nullptr;
+  a.Gpart = c->at<float>(c->lay.Gpart);
+  a.Fpart = c->at<double>(c->lay.Fpart);
+  a.Mp = c->dim.Mp;
+  a.Kp = c->dim.Kp;
+  a.Pp = c->dim.Pp;
+  a.nblocks = c->dim.nblocks;
+  a.S = c->dim.S;
+  a.ntiles = c->dim.ntiles;
+  a.gt = c->gt;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gmco_strerror(int s) {
+  switch (s) {
+    case GMCO_OK: return "ok";
+    case GMCO_EINVAL: return "invalid argument";
+    case GMCO_ENOMEM: return "out of device memory or workspace too small";
+    case GMCO_EHIP: return "HIP runtime error";
+    case GMCO_ESTATE: return "call out of order";
+    case GMCO_ENUMERIC: return "every plan is non-finite";
+    case GMCO_ENOLIB: return "no usable gfx950 device";
+    default: return "unknown status";
+  }
+}
+
+const char* gmco_last_error(const gmco_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int gmco_create(gmco_ctx** out, const gmco_opts* o) {
+  if (!out || !o) return GMCO_EINVAL;
+  *out = nullptr;
+  if (o->dtype < GMCO_DTYPE_F32 || o->dtype > GMCO_DTYPE_F32_ACC64) return GMCO_EINVAL;
+  if (o->history < 1 || o->history > GMCO_MAX_HISTORY) return GMCO_EINVAL;
+  if (o->max_plans < 1 || o->max_plans > (1 << 20)) return GMCO_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GMCO_ENOLIB;
+  if (o->device < 0 || o->device >= ndev) return GMCO_EINVAL;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, o->device) != hipSuccess) return GMCO_EHIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GMCO_ENOLIB;
+  gmco_ctx* c = new (std::nothrow) gmco_ctx();
+  if (!c) return GMCO_ENOMEM;
+  c->device = o->device;
+  c->dtype = o->dtype;
+  c->m = o->history;
+  c->Pmax = o->max_plans;
+  c->n_cu = prop.multiProcessorCount;
+  if (hipSetDevice(c->device) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_count, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    gmco_destroy(c);
+    return GMCO_EHIP;
+  }
+  *out = c;
+  return GMCO_OK;
+}
+
+int gmco_destroy(gmco_ctx* c) {
+  if (!c) return GMCO_OK;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  if (c->ws_owned && c->ws) hipFree(c->ws);
+  if (c->host_count) hipHostFree(c->host_count);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+  return GMCO_OK;
+}
+
+int gmco_set_stream(gmco_ctx* c, void* stream) {
+  if (!c) return GMCO_EINVAL;
+  c->stream = static_cast<hipStream_t>(stream);
+  return GMCO_OK;
+}
+
+int gmco_workspace_bytes(const gmco_ctx* c, int M, int K, size_t* bytes) {
+  if (!c || !bytes || M < 1 || K < 1 || K > GMCO_MAX_DWELLS) return GMCO_EINVAL;
+  const Dims d = make_dims(M, K, c->Pmax, c->n_cu);
+  *bytes = make_layout(d, kGmax, c->m, c->dtype, c->Pmax).total;
+  return GMCO_OK;
+}
+
+int gmco_bind_workspace(gmco_ctx* c, void* ptr, size_t bytes) {
+  if (!c) return GMCO_EINVAL;
+  if (ptr && (reinterpret_cast<uintptr_t>(ptr) & 255u)) return fail(c, GMCO_EINVAL, "workspace must be 256-byte aligned");
+  c->bound = ptr;
+  c->bound_bytes = ptr ? bytes : 0;
+  return GMCO_OK;
+}
+
+int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
+  if (!c || !cs) return GMCO_EINVAL;
+  const int M = cs->n_points, K = cs->n_dwells, G = cs->n_groups;
+  if (M < 1 || K < 1 || K > GMCO_MAX_DWELLS) return fail(c, GMCO_EINVAL, "n_points >= 1 and 1 <= n_dwells <= 512 required");
+  if (G < 1 || G > kGmax) return fail(c, GMCO_EINVAL, "n_groups must be 1..8");
+  if (!cs->group || !cs->group_params || !cs->dwell_xyz || (!cs->point_xyz && !cs->dose_rate))
+    return fail(c, GMCO_EINVAL, "missing case array");
+  if (!(cs->prescription_gy > 0.0) || !std::isfinite(cs->prescription_gy))
+    return fail(c, GMCO_EINVAL, "prescription must be > 0");
+  if (cs->target_group < 0 || cs->target_group >= G) return fail(c, GMCO_EINVAL, "target_group out of range");
+  if (!finite_all(cs->group_params, (size_t)G * 4)) return fail(c, GMCO_EINVAL, "non-finite group parameter");
+  for (int j = 0; j < G; ++j) {
+    const double* p = cs->group_params + 4 * j;
+    if (p[0] < 0 || p[3] < 0 || p[1] > p[2]) return fail(c, GMCO_EINVAL, "group parameters need w >= 0 and D_min <= D_max");
+  }
+  if (!finite_all(cs->dwell_xyz, (size_t)K * 3)) return fail(c, GMCO_EINVAL, "non-finite dwell position");
+  if (cs->point_xyz && !finite_all(cs->point_xyz, (size_t)M * 3)) return fail(c, GMCO_EINVAL, "non-finite point position");
+  if (cs->dose_rate) {
+    for (size_t i = 0; i < (size_t)M * K; ++i)
+      if (!std::isfinite(cs->dose_rate[i]) || cs->dose_rate[i] < 0.0) return fail(c, GMCO_EINVAL, "dose_rate must be finite and >= 0");
+  }
+  std::vector<int> counts(kGmax, 0);
+  for (int i = 0; i < M; ++i) {
+    const int g = cs->group[i];
+    if (g < 0 || g >= G) return fail(c, GMCO_EINVAL, "group index out of range");
+    counts[g] += 1;
+  }
+  if (counts[cs->target_group] == 0) return fail(c, GMCO_EINVAL, "target structure has no points");
+
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Dims d = make_dims(M, K, c->Pmax, c->n_cu);
+  const Layout L = make_layout(d, G, c->m, c->dtype, c->Pmax);
+  // arena: bound workspace, else a library allocation (reused when big enough)
+  if (c->bound) {
+    if (c->bound_bytes < L.total) return fail(c, GMCO_ENOMEM, "bound workspace smaller than gmco_workspace_bytes");
+    if (c->ws_owned && c->ws) hipFree(c->ws);
+    c->ws = c->bound;
+    c->ws_bytes = c->bound_bytes;
+    c->ws_owned = false;
+  } else if (!c->ws_owned || c->ws_bytes < L.total) {
+    if (c->ws_owned && c->ws) {
+      hipStreamSynchronize(c->stream);
+      hipFree(c->ws);
+    }
+    c->ws = nullptr;
+    c->ws_owned = false;
+    if (hipMalloc(&c->ws, L.total) != hipSuccess) {
+      c->ws = nullptr;
+      c->ws_bytes = 0;
+      return fail(c, GMCO_ENOMEM, "hipMalloc of the device arena failed");
+    }
+    c->ws_owned = true;
+    c->ws_bytes = L.total;
+  }
+  c->dim = d;
+  c->lay = L;
+  c->G = G;
+  c->rx = cs->prescription_gy;
+  c->target = cs->target_group;
+  c->case_loaded = false;
+  c->P = 0;
+
+  // points grouped by structure (stable), so every structure is one range
+  c->counts = counts;
+  c->offsets.assign(kGmax, 0);
+  for (int j = 1; j < kGmax; ++j) c->offsets[j] = c->offsets[j - 1] + counts[j - 1];
+  c->perm.assign(M, 0);
+  {
+    std::vector<int> cur(c->offsets);
+    for (int i = 0; i < M; ++i) c->perm[cur[cs->group[i]]++] = i;
+  }
+  std::vector<int> grp(d.Mp, kGmax);
+  for (int i = 0; i < M; ++i) grp[i] = cs->group[c->perm[i]];
+
+  double* stage = c->at<double>(L.stage);
+  double* st_D = stage;                         // M*K
+  double* st_dw = stage + (size_t)M * K;        // K*3
+  double* st_pt = st_dw + (size_t)K * 3;        // M*3
+  int rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.perm), c->perm.data(), (size_t)M * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.grp), grp.data(), (size_t)d.Mp * 4))) return rc;
+  if ((rc = copy_h2d(c, st_dw, cs->dwell_xyz, (size_t)K * 3 * 8))) return rc;
+  if (cs->point_xyz && (rc = copy_h2d(c, st_pt, cs->point_xyz, (size_t)M * 3 * 8))) return rc;
+  if (cs->dose_rate && (rc = copy_h2d(c, st_D, cs->dose_rate, (size_t)M * K * 8))) return rc;
+  std::vector<double> gp(kGmax * 4, 0.0), vol(kGmax, 0.0);
+  std::copy(cs->group_params, cs->group_params + 4 * G, gp.begin());
+  if (cs->group_volume_cc) std::copy(cs->group_volume_cc, cs->group_volume_cc + G, vol.begin());
+  if ((rc = copy_h2d(c, c->at<void>(L.gparams), gp.data(), gp.size() * 8))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.volume), vol.data(), vol.size() * 8))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.goff), c->offsets.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.gcnt), counts.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.counts), counts.data(), kGmax * 4))) return rc;
+  for (int j = 0; j <= kGmax; ++j) {
+    for (int k = 0; k < 4; ++k) c->gt.prm64[j][k] = j < G ? gp[4 * j + k] : 0.0;
+    c->gt.prm[j] = make_float4((float)c->gt.prm64[j][0], (float)c->gt.prm64[j][1],
+                               (float)c->gt.prm64[j][2], (float)c->gt.prm64[j][3]);
+  }
+
+  GMCO_HIP(c, launch_dose_rate(st_dw, cs->point_xyz ? st_pt : nullptr, cs->dose_rate ? st_D : nullptr,
+                               c->at<int>(L.perm), M, K, d.Mp, d.Kp, c->at<double>(L.D64), c->stream));
+  GMCO_HIP(c, launch_cast_dose(c->at<double>(L.D64), d.Mp, d.Kp, c->dtype, c->at<void>(L.Drun),
+                               c->at<void>(L.DT), c->at<float>(L.colscale), c->stream));
+  const int r0 = c->offsets[cs->target_group];
+  GMCO_HIP(c, launch_start_time(c->at<double>(L.D64), d.Kp, r0, r0 + counts[cs->target_group], c->rx,
+                                c->at<double>(L.t_bar), c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  c->case_loaded = true;
+  return GMCO_OK;
+}
+
+int gmco_set_weights(gmco_ctx* c, int P, const double* W, const double* t0) {
+  if (!c || !W) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  if (P < 1 || P > c->Pmax) return fail(c, GMCO_EINVAL, "n_plans out of 1..max_plans");
+  const int G = c->G, K = c->dim.K;
+  for (size_t i = 0; i < (size_t)P * G; ++i)
+    if (!std::isfinite(W[i]) || W[i] < 0.0) return fail(c, GMCO_EINVAL, "weights must be finite and >= 0");
+  if (t0) {
+    for (size_t i = 0; i < (size_t)P * K; ++i)
+      if (!std::isfinite(t0[i]) || t0[i] < 0.0) return fail(c, GMCO_EINVAL, "t0 must be finite and >= 0");
+  }
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Layout& L = c->lay;
+  int rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.Wst), W, (size_t)P * G * 8))) return rc;
+  if (t0 && (rc = copy_h2d(c, c->at<void>(L.t0st), t0, (size_t)P * K * 8))) return rc;
+  GMCO_HIP(c, launch_init_plans(P, c->dim.Pp, K, c->dim.Kp, t0 ? c->at<double>(L.t0st) : nullptr,
+                                c->at<double>(L.t_bar), c->at<double>(L.Wst), G, c->at<int>(L.counts),
+                                c->at<float>(L.xt), c->at<float>(L.x), c->at<float>(L.wn),
+                                c->at<double>(L.W64), c->at<PlanState>(L.ps), c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  c->P = P;
+  return GMCO_OK;
+}
+
+int gmco_evaluate(gmco_ctx* c, const double* x, double* F, double* g) {
+  if (!c || !x || !F || !g) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  const int P = c->P, K = c->dim.K;
+  if (!finite_all(x, (size_t)P * K)) return fail(c, GMCO_EINVAL, "x must be finite");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Layout& L = c->lay;
+  int rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.xst), x, (size_t)P * K * 8))) return rc;
+  GMCO_HIP(c, launch_x_to_device(c->at<double>(L.xst), P, c->dim.Pp, K, c->dim.Kp, c->at<float>(L.xe), c->stream));
+  EvalArgs a = eval_args(c, c->at<float>(L.xe), false);
+  GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+  GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, c->at<float>(L.xe), c->dim.S, P, c->dim.Pp, K,
+                                 c->dim.Kp, c->at<double>(L.Fst), c->at<double>(L.gst), c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(F, c->at<void>(L.Fst), (size_t)P * 8, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(g, c->at<void>(L.gst), (size_t)P * K * 8, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
+  if (!c || !r) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  if (r->max_iter < 0 || !(r->eps >= 0.0) || !(r->c1 > 0.0) || !(r->beta > 0.0 && r->beta < 1.0) ||
+      r->max_ls < 1 || r->check_every < 0)
+    return fail(c, GMCO_EINVAL, "bad run options");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  int* active = c->at<int>(L.active);
+  unsigned long long* work = c->at<unsigned long long>(L.work);
+  GMCO_HIP(c, hipMemsetAsync(active, 0, 2 * sizeof(int), c->stream));
+  GMCO_HIP(c, hipMemsetAsync(work, 0, sizeof(unsigned long long), c->stream));
+  GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), d.Pp, d.Kp,
+                            r->max_iter, r->resume_stopped, c->stream));
+  UpdateArgs u{};
+  u.Gpart = c->at<float>(L.Gpart);
+  u.Fpart = c->at<double>(L.Fpart);
+  u.x = c->at<float>(L.x);
+  u.g = c->at<float>(L.g);
+  u.dir = c->at<float>(L.dir);
+  u.xt = c->at<float>(L.xt);
+  u.Sh = c->at<float>(L.Sh);
+  u.Yh = c->at<float>(L.Yh);
+  u.rho = c->at<double>(L.rho);
+  u.ps = c->at<PlanState>(L.ps);
+  u.active_count = active;
+  u.Kp = d.Kp;
+  u.Pp = d.Pp;
+  u.S = d.S;
+  u.m = c->m;
+  u.K = d.K;
+  u.max_iter = r->max_iter;
+  u.max_ls = r->max_ls;
+  u.eps = r->eps;
+  u.c1 = r->c1;
+  u.beta = r->beta;
+  EvalArgs a = eval_args(c, c->at<float>(L.xt), true);
+  a.work = work;
+  const int check = r->check_every > 0 ? r->check_every : 16;
+  const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
+  // optional per-launch timing: 4 events per round of one check block
+  std::vector<hipEvent_t> ev;
+  if (r->time_kernels) {
+    ev.resize((size_t)4 * check, nullptr);
+    for (auto& e : ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        for (auto& f : ev)
+          if (f) hipEventDestroy(f);
+        return fail(c, GMCO_EHIP, "hipEventCreate failed");
+      }
+    }
+  }
+  struct EventGuard {
+    std::vector<hipEvent_t>& v;
+    ~EventGuard() {
+      for (auto& e : v)
+        if (e) hipEventDestroy(e);
+    }
+  } guard{ev};
+  double eval_ms = 0.0, update_ms = 0.0;
+  auto harvest = [&](int n) -> hipError_t {
+    for (int i = 0; i < n; ++i) {
+      float a_ms = 0.f, b_ms = 0.f;
+      hipError_t e = hipEventElapsedTime(&a_ms, ev[4 * i], ev[4 * i + 1]);
+      if (e != hipSuccess) return e;
+      e = hipEventElapsedTime(&b_ms, ev[4 * i + 2], ev[4 * i + 3]);
+      if (e != hipSuccess) return e;
+      eval_ms += a_ms;
+      update_ms += b_ms;
+    }
+    return hipSuccess;
+  };
+  GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
+  long long round = 0;
+  int in_block = 0;
+  for (; round < max_rounds; ++round) {
+    u.round = (int)round;
+    if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
+    GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+    if (r->time_kernels) {
+      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 1], c->stream));
+      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 2], c->stream));
+    }
+    GMCO_HIP(c, launch_update(u, c->stream));
+    if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 3], c->stream));
+    ++in_block;
+    if ((round + 1) % check == 0) {
+      GMCO_HIP(c, hipMemcpyAsync(c->host_count, active + (round & 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      GMCO_HIP(c, hipStreamSynchronize(c->stream));
+      if (r->time_kernels) GMCO_HIP(c, harvest(in_block));
+      in_block = 0;
+      if (*c->host_count == 0) {
+        ++round;
+        break;
+      }
+    }
+  }
+  GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
+  GMCO_HIP(c, hipEventSynchronize(c->ev1));
+  if (r->time_kernels) GMCO_HIP(c, harvest(in_block));
+  unsigned long long done = 0;
+  GMCO_HIP(c, hipMemcpy(&done, work, sizeof(done), hipMemcpyDeviceToHost));
+  std::vector<PlanState> ps(c->P);
+  GMCO_HIP(c, hipMemcpy(ps.data(), c->at<void>(L.ps), (size_t)c->P * sizeof(PlanState), hipMemcpyDeviceToHost));
+  gmco_run_info inf{};
+  inf.rounds = (int)round;
+  for (const PlanState& s : ps) {
+    inf.n_converged += s.status == ST_CONVERGED;
+    inf.n_maxiter += s.status == ST_MAXITER;
+    inf.n_ls_fail += s.status == ST_LSFAIL;
+    inf.n_nonfinite += s.status == ST_NONFINITE;
+    inf.max_iters = std::max(inf.max_iters, s.iter);
+  }
+  float ms = 0.f;
+  GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  inf.device_ms = ms;
+  inf.eval_ms = (float)eval_ms;
+  inf.update_ms = (float)update_ms;
+  inf.eval_launches = (int)round;
+  inf.eval_work = (double)done / (double)(d.S * d.ntiles);
+  if (info) *info = inf;
+  if (inf.n_nonfinite == c->P) return fail(c, GMCO_ENUMERIC, "every plan has a non-finite objective");
+  return GMCO_OK;
+}
+
+int gmco_get_dwell_times(gmco_ctx* c, double* t) {
+  if (!c || !t) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const int K = c->dim.K;
+  double* tst = c->at<double>(c->lay.gst);
+  GMCO_HIP(c, launch_export_t(c->at<float>(c->lay.x), c->P, K, c->dim.Kp, tst, K, c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(t, tst, (size_t)c->P * K * 8, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+int gmco_get_weights_x(gmco_ctx* c, double* x) {
+  if (!c || !x) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const int K = c->dim.K, Kp = c->dim.Kp;
+  std::vector<float> xs((size_t)c->P * Kp);
+  GMCO_HIP(c, hipMemcpyAsync(xs.data(), c->at<void>(c->lay.x), xs.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  for (int p = 0; p < c->P; ++p)
+    for (int l = 0; l < K; ++l) x[(size_t)p * K + l] = xs[(size_t)p * Kp + l];
+  return GMCO_OK;
+}
+
+int gmco_get_metrics(gmco_ctx* c, gmco_plan_metrics* out) {
+  if (!c || !out) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  GMCO_HIP(c, launch_export_t(c->at<float>(L.x), d.Pp, d.K, d.Kp, c->at<double>(L.t64), d.Kp, c->stream));
+  GMCO_HIP(c, launch_dose64(c->at<double>(L.D64), c->at<double>(L.t64), d.Mp, d.Kp, d.Pp, c->at<double>(L.d64), c->stream));
+  GMCO_HIP(c, launch_metrics(c->at<double>(L.d64), c->at<double>(L.W64), c->at<PlanState>(L.ps), c->P, d.Mp,
+                             c->at<int>(L.goff), c->at<int>(L.gcnt), c->G, c->at<double>(L.gparams),
+                             c->at<double>(L.volume), c->rx, c->at<gmco_plan_metrics>(L.metrics), c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(out, c->at<void>(L.metrics), (size_t)c->P * sizeof(gmco_plan_metrics),
+                             hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+int gmco_get_dose_rate(gmco_ctx* c, double* D64, double* Drun) {
+  if (!c) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Dims& d = c->dim;
+  const size_t MK = (size_t)d.Mp * d.Kp;
+  std::vector<double> h64;
+  std::vector<float> hr;
+  if (D64) {
+    h64.resize(MK);
+    GMCO_HIP(c, hipMemcpyAsync(h64.data(), c->at<void>(c->lay.D64), MK * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (Drun) {
+    if (dtype_bytes(c->dtype) != 4) return fail(c, GMCO_EINVAL, "run-dtype export is FP32 only");
+    hr.resize(MK);
+    GMCO_HIP(c, hipMemcpyAsync(hr.data(), c->at<void>(c->lay.Drun), MK * 4, hipMemcpyDeviceToHost, c->stream));
+  }
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < d.M; ++i) {
+    const size_t dst = (size_t)c->perm[i] * d.K;
+    for (int l = 0; l < d.K; ++l) {
+      if (D64) D64[dst + l] = h64[(size_t)i * d.Kp + l];
+      if (Drun) Drun[dst + l] = hr[(size_t)i * d.Kp + l];
+    }
+  }
+  return GMCO_OK;
+}
+
+int gmco_get_start_time(gmco_ctx* c, double* t_bar) {
+  if (!c || !t_bar) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  GMCO_HIP(c, hipMemcpyAsync(t_bar, c->at<void>(c->lay.t_bar), 8, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+}  // extern "C"

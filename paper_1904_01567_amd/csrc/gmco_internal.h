@@ -1,0 +1,118 @@
+// Internal types shared by the gMCO device kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "gmco.h"
+
+namespace gmco {
+
+constexpr int kGmax = GMCO_MAX_GROUPS;
+constexpr int kBM = 16;   // dose points per inner block of the evaluation kernel
+constexpr int kPT = 64;   // plans per workgroup tile of the evaluation kernel
+constexpr int kKAlign = 32;
+
+// Internal plan states; 0..5 match gmco_plan_status.
+enum : int {
+  ST_RUNNING = 0,
+  ST_CONVERGED = 1,
+  ST_MAXITER = 2,
+  ST_LSFAIL = 3,
+  ST_NONFINITE = 4,
+  ST_INACTIVE = 5,
+  ST_INIT = 6  // the point in xt is to be taken as the current iterate
+};
+
+__host__ __device__ inline bool state_active(int s) { return s == ST_RUNNING || s == ST_INIT; }
+
+// Per-plan scalars of the batched L-BFGS state machine.
+struct PlanState {
+  double F;      // objective at x
+  double Fprev;  // objective before the last accepted step
+  double alpha;  // current trial step
+  double gtp;    // g' p of the current direction
+  int status;
+  int iter;      // accepted steps
+  int ntrial;    // rejected trials of the current iteration
+  int hcount;    // history pairs held
+  int hhead;     // next ring slot
+  int nevals;    // objective evaluations
+  int pad0, pad1;
+};
+static_assert(sizeof(PlanState) == 64, "PlanState layout");
+
+// Eq. 1 parameters per structure: (w_min, D_min, D_max, w_max); entry kGmax
+// is the all-zero row used by padding points.
+struct GroupTable {
+  float4 prm[kGmax + 1];
+  double prm64[kGmax + 1][4];
+};
+
+struct EvalArgs {
+  const void* D;          // [Mp][Kp] dose-rate matrix in the run dtype
+  const void* DT;         // [Kp][Mp] transposed copy (BF16 / FP8 only)
+  const float* colscale;  // [Kp] FP8 column scales (NULL otherwise)
+  const int* grp;         // [Mp] structure index, kGmax for padding
+  const float* x;         // [Pp][Kp] points to evaluate (dwell weights)
+  const float* wn;        // [Pp][kGmax] w_j / N_j
+  const PlanState* ps;    // plan states; NULL evaluates every tile
+  float* Gpart;           // [S][Pp][Kp] split-M partial back-projections
+  double* Fpart;          // [S][Pp] split-M partial objectives
+  unsigned long long* work;  // optional count of workgroups that did not skip
+  int Mp, Kp, Pp;
+  int nblocks;            // Mp / kBM
+  int S;                  // M splits
+  int ntiles;             // Pp / kPT
+  GroupTable gt;
+};
+
+struct UpdateArgs {
+  const float* Gpart;
+  const double* Fpart;
+  float* x;       // [Pp][Kp] current iterate
+  float* g;       // [Pp][Kp] gradient at x
+  float* dir;     // [Pp][Kp] search direction
+  float* xt;      // [Pp][Kp] point to evaluate next
+  float* Sh;      // [Pp][m][Kp]
+  float* Yh;      // [Pp][m][Kp]
+  double* rho;    // [Pp][m]
+  PlanState* ps;
+  int* active_count;  // [2]
+  int Kp, Pp, S, m, K;
+  int max_iter, max_ls;
+  double eps, c1, beta;
+  int round;
+};
+
+// ---- launchers (each defined next to its kernels) ----
+hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
+                            const int* perm, int M, int K, int Mp, int Kp, double* D64,
+                            hipStream_t st);
+hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, void* Drun, void* DT,
+                            float* colscale, hipStream_t st);
+hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_end,
+                             double prescription, double* t_bar, hipStream_t st);
+hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, const double* t_bar,
+                             const double* W, int G, const int* counts, float* xt, float* x,
+                             float* wn, double* W64, PlanState* ps, hipStream_t st);
+hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st);
+hipError_t launch_update(const UpdateArgs& a, hipStream_t st);
+hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
+                              int P, int Pp, int K, int Kp, double* F, double* g,
+                              hipStream_t st);
+hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int Pp, int Kp, int max_iter,
+                         int resume_stopped, hipStream_t st);
+hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,
+                           hipStream_t st);
+hipError_t launch_x_to_device(const double* x_host_dev, int P, int Pp, int K, int Kp, float* xe,
+                              hipStream_t st);
+hipError_t launch_dose64(const double* D64, const double* t64, int Mp, int Kp, int Pp,
+                         double* d64, hipStream_t st);
+hipError_t launch_metrics(const double* d64, const double* W64, const PlanState* ps, int P,
+                          int Mp, const int* goff, const int* gcnt, int G, const double* gparams,
+                          const double* volume_cc, double prescription, gmco_plan_metrics* out,
+                          hipStream_t st);
+
+}  // namespace gmco

@@ -1,0 +1,220 @@
+// Final-plan quantities in FP64: t = x^2, the dose of every point
+// (eq. (dose)), eq. (obj) re-evaluated, and the DVH metrics of Sec. 2.3.1.
+#include "gmco_internal.h"
+
+namespace gmco {
+namespace {
+
+__global__ void k_export_t(const float* __restrict__ x, int P, int K, int Kp,
+                           double* __restrict__ t64, int Kp_out) {
+  const int p = blockIdx.x;
+  if (p >= P) return;
+  for (int l = threadIdx.x; l < Kp_out; l += blockDim.x) {
+    double v = 0.0;
+    if (l < K) {
+      const double xv = (double)x[(size_t)p * Kp + l];
+      v = xv * xv;
+    }
+    t64[(size_t)p * Kp_out + l] = v;
+  }
+}
+
+// d64[p][i] = sum_l D64[i][l] t64[p][l]; 64 points x 64 plans per workgroup,
+// 4 x 4 outputs per thread, 32-dwell slices staged in LDS.
+__global__ __launch_bounds__(256) void k_dose64(const double* __restrict__ D64,
+                                                const double* __restrict__ t64, int Mp, int Kp,
+                                                int Pp, double* __restrict__ d64) {
+  __shared__ double sD[64][33];
+  __shared__ double sT[64][33];
+  const int i0 = blockIdx.x * 64;
+  const int p0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 15;  // points i0 + tx + 16 a
+  const int ty = threadIdx.x >> 4;  // plans  p0 + ty + 16 b
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < Kp; k0 += 32) {
+    for (int idx = threadIdx.x; idx < 64 * 32; idx += 256) {
+      const int r = idx >> 5, c = idx & 31;
+      const int gi = i0 + r, gp = p0 + r, gk = k0 + c;
+      sD[r][c] = (gi < Mp && gk < Kp) ? D64[(size_t)gi * Kp + gk] : 0.0;
+      sT[r][c] = (gp < Pp && gk < Kp) ? t64[(size_t)gp * Kp + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < 32; ++c) {
+      double dv[4], tv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dv[a] = sD[tx + 16 * a][c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) tv[b] = sT[ty + 16 * b][c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(dv[a], tv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int gi = i0 + tx + 16 * a, gp = p0 + ty + 16 * b;
+      if (gi < Mp && gp < Pp) d64[(size_t)gp * Mp + gi] = acc[a][b];
+    }
+}
+
+// k-th largest of the keys (bit patterns of non-negative doubles order like
+// their values), radix select over 8-bit digits from the most significant.
+struct SelectState {
+  unsigned long long prefix;
+  unsigned long long mask;
+  int k;
+};
+
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per (plan, structure).
+__global__ __launch_bounds__(256) void k_metrics_group(
+    const double* __restrict__ d64, int P, int Mp, const int* __restrict__ goff,
+    const int* __restrict__ gcnt, int G, const double* __restrict__ gparams,
+    const double* __restrict__ volume_cc, double rx, gmco_plan_metrics* __restrict__ out) {
+  __shared__ double red[256];
+  __shared__ unsigned int h10[256], h90[256];
+  __shared__ SelectState sel[2];
+  const int p = blockIdx.x;
+  const int j = blockIdx.y;
+  if (p >= P) return;
+  gmco_plan_metrics* m = out + p;
+  if (j >= G) {
+    if (threadIdx.x == 0 && j < kGmax) {
+      m->f_organ[j] = 0.0;
+      m->V100_pct[j] = 0.0;
+      m->V75_cc[j] = 0.0;
+      m->D10_pct[j] = 0.0;
+      m->D90_pct[j] = 0.0;
+    }
+    return;
+  }
+  const int N = gcnt[j];
+  const double* __restrict__ d = d64 + (size_t)p * Mp + goff[j];
+  const double wmin = gparams[4 * j + 0], dmin = gparams[4 * j + 1];
+  const double dmax = gparams[4 * j + 2], wmax = gparams[4 * j + 3];
+  const double thr100 = rx, thr75 = 0.75 * rx;
+
+  double fs = 0.0, c100 = 0.0, c75 = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double v = d[i];
+    if (v < dmin) fs += wmin * ((dmin - v) * (dmin - v));
+    else if (v > dmax) fs += wmax * ((v - dmax) * (v - dmax));
+    c100 += (v >= thr100) ? 1.0 : 0.0;
+    c75 += (v >= thr75) ? 1.0 : 0.0;
+  }
+  fs = block_sum(fs, red);
+  c100 = block_sum(c100, red);
+  c75 = block_sum(c75, red);
+
+  // D10 / D90: k = max(1, ceil(x N / 100)) in integers
+  if (threadIdx.x == 0) {
+    sel[0].prefix = 0ull;
+    sel[0].mask = 0ull;
+    sel[0].k = max(1, (10 * N + 99) / 100);
+    sel[1].prefix = 0ull;
+    sel[1].mask = 0ull;
+    sel[1].k = max(1, (90 * N + 99) / 100);
+  }
+  __syncthreads();
+  for (int shift = 56; shift >= 0 && N > 0; shift -= 8) {
+    h10[threadIdx.x] = 0u;
+    h90[threadIdx.x] = 0u;
+    __syncthreads();
+    const unsigned long long pf0 = sel[0].prefix, mk0 = sel[0].mask;
+    const unsigned long long pf1 = sel[1].prefix, mk1 = sel[1].mask;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const unsigned long long key = (unsigned long long)__double_as_longlong(d[i]);
+      const unsigned dig = (unsigned)((key >> shift) & 0xffull);
+      if ((key & mk0) == pf0) atomicAdd(&h10[dig], 1u);
+      if ((key & mk1) == pf1) atomicAdd(&h90[dig], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      unsigned int* h = threadIdx.x == 0 ? h10 : h90;
+      SelectState& s = sel[threadIdx.x];
+      int k = s.k;
+      int dsel = 0;
+      for (int dg = 255; dg >= 0; --dg) {
+        const int c = (int)h[dg];
+        if (k <= c) {
+          dsel = dg;
+          break;
+        }
+        k -= c;
+      }
+      s.k = k;
+      s.prefix |= ((unsigned long long)dsel) << shift;
+      s.mask |= 0xffull << shift;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n = N > 0 ? (double)N : 1.0;
+    m->f_organ[j] = fs / n;
+    m->V100_pct[j] = 100.0 * (c100 / n);
+    m->V75_cc[j] = (volume_cc ? volume_cc[j] : 0.0) * (c75 / n);
+    m->D10_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[0].prefix) / rx : 0.0;
+    m->D90_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[1].prefix) / rx : 0.0;
+  }
+}
+
+__global__ void k_metrics_final(const double* __restrict__ W64, const PlanState* __restrict__ ps,
+                                int P, int G, gmco_plan_metrics* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  gmco_plan_metrics* m = out + p;
+  double F = 0.0;
+  for (int j = 0; j < G; ++j) F += W64[(size_t)p * kGmax + j] * m->f_organ[j];
+  m->F64 = F;
+  m->F_run = ps[p].F;
+  m->iterations = ps[p].iter;
+  m->evaluations = ps[p].nevals;
+  m->status = ps[p].status == ST_INIT ? ST_RUNNING : ps[p].status;
+  m->reserved = 0;
+}
+
+}  // namespace
+
+hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_export_t, dim3(P), dim3(128), 0, st, x, P, K, Kp, t64, Kp_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dose64(const double* D64, const double* t64, int Mp, int Kp, int Pp,
+                         double* d64, hipStream_t st) {
+  dim3 grid((Mp + 63) / 64, (Pp + 63) / 64);
+  hipLaunchKernelGGL(k_dose64, grid, dim3(256), 0, st, D64, t64, Mp, Kp, Pp, d64);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics(const double* d64, const double* W64, const PlanState* ps, int P,
+                          int Mp, const int* goff, const int* gcnt, int G, const double* gparams,
+                          const double* volume_cc, double prescription, gmco_plan_metrics* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_metrics_group, dim3(P, kGmax), dim3(256), 0, st, d64, P, Mp, goff, gcnt,
+                     G, gparams, volume_cc, prescription, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_metrics_final, dim3((P + 127) / 128), dim3(128), 0, st, W64, ps, P, G,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace gmco

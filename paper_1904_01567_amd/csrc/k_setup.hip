@@ -1,0 +1,160 @@
+// Case and batch set-up kernels: dose-rate matrix (Sec. 2.2.1 step (i)),
+// its run-dtype copy, the default start time and the per-plan state.
+#include "gmco_internal.h"
+
+namespace gmco {
+namespace {
+
+// Point-source law of the synthetic cases: (1 - 0.01 r) / max(r, 0.1 cm)^2.
+// Rows follow the library's point order (grouped by structure): row i is the
+// caller's point perm[i].  Padding rows and columns are zero.
+__global__ void k_dose_rate(const double* __restrict__ dwell, const double* __restrict__ pts,
+                            const double* __restrict__ user_D, const int* __restrict__ perm,
+                            int M, int K, int Mp, int Kp, double* __restrict__ D64) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (l >= Kp || i >= Mp) return;
+  double v = 0.0;
+  if (i < M && l < K) {
+    const int src = perm[i];
+    if (user_D != nullptr) {
+      v = user_D[(size_t)src * K + l];
+    } else {
+      const double dx = pts[3 * src + 0] - dwell[3 * l + 0];
+      const double dy = pts[3 * src + 1] - dwell[3 * l + 1];
+      const double dz = pts[3 * src + 2] - dwell[3 * l + 2];
+      const double r = sqrt(dx * dx + dy * dy + dz * dz);
+      const double rc = r > 0.1 ? r : 0.1;
+      v = (1.0 - 0.01 * r) / (rc * rc);
+    }
+  }
+  D64[(size_t)i * Kp + l] = v;
+}
+
+__global__ void k_cast_f32(const double* __restrict__ D64, size_t n, float* __restrict__ out) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x)
+    out[idx] = (float)D64[idx];
+}
+
+// t_bar = Rx / mean over the target rows of sum_l D_il, one workgroup, fixed
+// summation order.
+__global__ void k_start_time(const double* __restrict__ D64, int Kp, int r0, int r1, double rx,
+                             double* __restrict__ t_bar) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    double rs = 0.0;
+    for (int l = 0; l < Kp; ++l) rs += D64[(size_t)i * Kp + l];
+    acc += rs;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = red[0] / (double)(r1 - r0);
+    *t_bar = (r1 > r0 && mean > 0.0) ? rx / mean : 0.0;
+  }
+}
+
+// Start point and weights of every plan slot.  Inactive slots (p >= P) get
+// zero weights and the INACTIVE state.
+__global__ void k_init_plans(int P, int Pp, int K, int Kp, const double* __restrict__ t0,
+                             const double* __restrict__ t_bar, const double* __restrict__ W,
+                             int G, const int* __restrict__ counts, float* __restrict__ xt,
+                             float* __restrict__ x, float* __restrict__ wn,
+                             double* __restrict__ W64, PlanState* __restrict__ ps) {
+  const int p = blockIdx.x;
+  if (p >= Pp) return;
+  const bool live = p < P;
+  const double tb = *t_bar;
+  for (int l = threadIdx.x; l < Kp; l += blockDim.x) {
+    float v = 0.f;
+    if (live && l < K) {
+      const double t = t0 ? t0[(size_t)p * K + l] : tb;
+      v = (float)sqrt(t > 0.0 ? t : 0.0);
+    }
+    xt[(size_t)p * Kp + l] = v;
+    x[(size_t)p * Kp + l] = v;
+  }
+  if (threadIdx.x < kGmax) {
+    const int j = threadIdx.x;
+    double w = 0.0;
+    if (live && j < G) w = W[(size_t)p * G + j];
+    W64[(size_t)p * kGmax + j] = w;
+    wn[(size_t)p * kGmax + j] = (j < G && counts[j] > 0) ? (float)(w / (double)counts[j]) : 0.f;
+  }
+  if (threadIdx.x == 0) {
+    PlanState s;
+    s.F = 0.0;
+    s.Fprev = 0.0;
+    s.alpha = 0.0;
+    s.gtp = 0.0;
+    s.status = live ? ST_INIT : ST_INACTIVE;
+    s.iter = 0;
+    s.ntrial = 0;
+    s.hcount = 0;
+    s.hhead = 0;
+    s.nevals = 0;
+    s.pad0 = 0;
+    s.pad1 = 0;
+    ps[p] = s;
+  }
+}
+
+// Dwell weights given by the caller (FP64, P x K) into the padded FP32 layout.
+__global__ void k_x_to_device(const double* __restrict__ xin, int P, int K, int Kp,
+                              float* __restrict__ xe) {
+  const int p = blockIdx.x;
+  for (int l = threadIdx.x; l < Kp; l += blockDim.x)
+    xe[(size_t)p * Kp + l] = (p < P && l < K) ? (float)xin[(size_t)p * K + l] : 0.f;
+}
+
+}  // namespace
+
+hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
+                            const int* perm, int M, int K, int Mp, int Kp, double* D64,
+                            hipStream_t st) {
+  dim3 grid((Kp + 127) / 128, Mp);
+  hipLaunchKernelGGL(k_dose_rate, grid, dim3(128), 0, st, dwell_xyz, pt_xyz, user_D, perm, M, K,
+                     Mp, Kp, D64);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, void* Drun, void* DT,
+                            float* colscale, hipStream_t st) {
+  (void)DT;
+  (void)colscale;
+  const size_t n = (size_t)Mp * Kp;
+  if (dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64) {
+    hipLaunchKernelGGL(k_cast_f32, dim3(1024), dim3(256), 0, st, D64, n, (float*)Drun);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_end,
+                             double prescription, double* t_bar, hipStream_t st) {
+  hipLaunchKernelGGL(k_start_time, dim3(1), dim3(1024), 0, st, D64, Kp, row_begin, row_end,
+                     prescription, t_bar);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, const double* t_bar,
+                             const double* W, int G, const int* counts, float* xt, float* x,
+                             float* wn, double* W64, PlanState* ps, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_plans, dim3(Pp), dim3(128), 0, st, P, Pp, K, Kp, t0, t_bar, W, G,
+                     counts, xt, x, wn, W64, ps);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_to_device(const double* x_host_dev, int P, int Pp, int K, int Kp, float* xe,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_x_to_device, dim3(Pp), dim3(128), 0, st, x_host_dev, P, K, Kp, xe);
+  return hipGetLastError();
+}
+
+}  // namespace gmco

@@ -436,3 +436,12 @@ def test_plan_metrics_structure_volumes():
                        c.volume_cc, 15.0)[0]
     np.testing.assert_allclose(m["V75_cc"], c.volume_cc)
     np.testing.assert_allclose(m["V100_pct"], 100.0)
+
+
+def test_library_class_solution_matches_golden():
+    # the product package keeps its own copy of Table 1
+    from paper_1904_01567_amd import class_solution as cs
+    rows = _read_table1()
+    for i, o in enumerate(cs.STRUCTURES):
+        np.testing.assert_array_equal(cs.SURFACE[i], rows[(o, "surface")])
+        np.testing.assert_array_equal(cs.VOLUME[i], rows[(o, "volume")])
