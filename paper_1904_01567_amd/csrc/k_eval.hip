@@ -159,18 +159,19 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
     //      (eq. 1, the bracket of eq. 2, eq. (obj) weights) ----
     float phi[4];
     if constexpr (ACC64) {
-      d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      // four independent accumulation chains keep the FP64 pipe busy
+      d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
         const float4 av = *reinterpret_cast<const float4*>(&sD[n * KS + 16 * k + 4 * q]);
         acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
         acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
-        acc0 = mfma_f64(av.z, tf[4 * k + 2], acc0);
-        acc1 = mfma_f64(av.w, tf[4 * k + 3], acc1);
+        acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
+        acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double d = acc0[r] + acc1[r];
+        const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
         const int gi = sG[q + 4 * r];
         const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
         double kap = 0.0, dev = 0.0;

@@ -14,16 +14,19 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
-
-import numpy as np  # noqa: E402
 
 import cases  # noqa: E402
 import oracle as O  # noqa: E402
 
 SAMPLE = [0, 1, 2, 63, 64, 127, 128, 255, 256, 400, 511, 512, 700, 900, 998, 999]
+# 48 more plans drawn without replacement from the rest (seeded)
+_rest = sorted(set(range(1000)) - set(SAMPLE))
+SAMPLE = SAMPLE + sorted(np.random.default_rng(77).choice(_rest, 48, replace=False).tolist())
 # accepted-step counts at which each plan's objective is recorded
 CHECKPOINTS = [25, 50, 100, 150, 200, 300, 400, 500, 750, 1000, 1250, 1500, 2000, 2500, 3000,
                4000, 5000, 6000, 8000, 10000, 12000, 16000, 20000]
