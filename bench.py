@@ -40,6 +40,10 @@ PEAK_F64 = 78.6
 PEAK_F32 = 157.3
 
 
+DTYPE_NAMES = {"f32acc64": "f32 operands, f64-accumulated dose", "f32": "f32", "bf16": "bf16"}
+PEAK_BF16 = 2500.0
+
+
 def eval_peak_tflops(dtype: str) -> float:
     """Peak of the fused evaluation: half its FLOPs are the dose product, half
     the back-projection; with FP64 accumulation of the dose the two halves run
@@ -47,6 +51,8 @@ def eval_peak_tflops(dtype: str) -> float:
     mean."""
     if dtype == "f32acc64":
         return 2.0 / (1.0 / PEAK_F64 + 1.0 / PEAK_F32)
+    if dtype == "bf16":
+        return PEAK_BF16
     return PEAK_F32
 
 
@@ -107,7 +113,10 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32"])
+    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32", "bf16"])
+    ap.add_argument("--ladder", type=str, default=None,
+                    help="precision ladder, e.g. bf16:150,f32acc64:2000 (iteration caps are "
+                         "cumulative); the context is created with the first dtype")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -143,11 +152,14 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n}), flush=True)
         return 0
-    iters = args.iters or ITERS[args.dtype]
+    stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
+    if args.ladder:
+        stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]
+    iters = stages[-1][1]
     case = cases.case_c2()
     W = cases.weights_c2(args.plans)
     golden = load_golden()
-    pl = Planner(dtype=args.dtype, max_plans=args.plans)
+    pl = Planner(dtype=stages[0][0], max_plans=args.plans)
     t_load = time.perf_counter()
     pl.load(case, class_solution.VOLUME)
     torch.cuda.synchronize()
@@ -163,7 +175,13 @@ def main(argv=None) -> int:
 
     def step(time_kernels=False):
         pl.set_weights(W)
-        info = pl.optimize(max_iter=iters, time_kernels=time_kernels)
+        infos = []
+        for k, (dt, cap) in enumerate(stages):
+            infos.append(pl.optimize(max_iter=cap, time_kernels=time_kernels, dtype=dt,
+                                     resume_stopped=k > 0))
+        info = {key: sum(i[key] for i in infos) for key in
+                ("rounds", "device_ms", "eval_ms", "update_ms", "eval_launches", "eval_work")}
+        info["stages"] = infos
         t = pl.dwell_times()
         m = pl.metrics()
         return info, t, m
@@ -184,14 +202,15 @@ def main(argv=None) -> int:
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.plans / (ms_per_step / 1e3)
 
-    # roofline of the fused evaluation kernel over the timed region
+    # roofline of the fused evaluation kernel of the last (dominant) stage
     M, K, P = case.M, case.K, args.plans
     flops_full = 4.0 * M * K * P          # dose product + back-projection, unpadded
-    eval_ms = sum(i["eval_ms"] for i in infos)
-    launches = sum(i["eval_launches"] for i in infos)
-    work = sum(i["eval_work"] for i in infos)
+    last = [i["stages"][-1] for i in infos]
+    eval_ms = sum(i["eval_ms"] for i in last)
+    launches = sum(i["eval_launches"] for i in last)
+    work = sum(i["eval_work"] for i in last)
     achieved = work * flops_full / (eval_ms / 1e3) / 1e12
-    peak = eval_peak_tflops(args.dtype)
+    peak = eval_peak_tflops(stages[-1][0])
     tol = tolerance_report(m, golden)
     upd_ms = sum(i["update_ms"] for i in infos)
 
@@ -207,19 +226,22 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 operands, f64-accumulated dose" if args.dtype == "f32acc64" else "f32",
+        "dtype": DTYPE_NAMES[stages[-1][0]] if len(stages) == 1 else
+                 " -> ".join(DTYPE_NAMES[d] for d, _ in stages),
         "data": "synthetic",
         "config": {
             "workload": f"prostate HDR case, {K} dwells x {M} points, {P} hidden-weight "
                         f"vectors, L-BFGS m=10, {iters} iterations per plan",
             "dwells": K, "points": M, "plans": P, "iterations": iters,
-            "lbfgs_history": 10, "eval_dtype": args.dtype,
+            "lbfgs_history": 10, "stages": [f"{d}:{n}" for d, n in stages],
         },
         "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
         "breakdown_ms_per_step": {
-            "eval_kernels": eval_ms / args.steps,
+            "eval_kernels": sum(i["eval_ms"] for i in infos) / args.steps,
             "update_kernels": upd_ms / args.steps,
-            "rounds": launches / args.steps,
+            "rounds": sum(i["rounds"] for i in infos) / args.steps,
+            "rounds_per_stage": [sum(i["stages"][k]["rounds"] for i in infos) / args.steps
+                                 for k in range(len(stages))],
             "load_case_once_ms": 1e3 * t_load,
         },
         "roofline": {

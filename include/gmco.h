@@ -108,7 +108,12 @@ typedef struct {
   int check_every;    /* rounds between host checks of the active-plan count (0 -> 16) */
   int time_kernels;   /* 1: time every evaluation and update launch with HIP events */
   int resume_stopped; /* 1: plans stopped as CONVERGED or LS_FAIL iterate again
-                         (e.g. after a change of dwell set or precision); 0: they stay */
+                         (e.g. after a change of precision); 0: they stay */
+  int dtype;          /* gmco_dtype of this run's evaluations, -1: the context's.
+                         F32 and F32_ACC64 are always available; BF16 and FP8 need a
+                         context created with that dtype.  Successive runs with
+                         rising precision form a precision ladder on one state. */
+  int reserved;
 } gmco_run;
 
 typedef struct {

@@ -55,7 +55,8 @@ class gmco_case(C.Structure):
 class gmco_run(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("eps", C.c_double), ("c1", C.c_double),
                 ("beta", C.c_double), ("max_ls", C.c_int), ("check_every", C.c_int),
-                ("time_kernels", C.c_int), ("resume_stopped", C.c_int)]
+                ("time_kernels", C.c_int), ("resume_stopped", C.c_int), ("dtype", C.c_int),
+                ("reserved", C.c_int)]
 
 
 class gmco_run_info(C.Structure):
@@ -235,9 +236,10 @@ class Planner:
 
     def optimize(self, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
                  max_ls: int = 30, check_every: int = 16, time_kernels: bool = False,
-                 resume_stopped: bool = False) -> dict:
+                 resume_stopped: bool = False, dtype: Optional[str] = None) -> dict:
         r = gmco_run(int(max_iter), float(eps), float(c1), float(beta), int(max_ls),
-                     int(check_every), int(bool(time_kernels)), int(bool(resume_stopped)))
+                     int(check_every), int(bool(time_kernels)), int(bool(resume_stopped)),
+                     -1 if dtype is None else DTYPES[dtype], 0)
         info = gmco_run_info()
         self._check(self.lib.gmco_optimize(self._ctx, C.byref(r), C.byref(info)), "optimize")
         return {k: getattr(info, k) for k, _ in gmco_run_info._fields_}

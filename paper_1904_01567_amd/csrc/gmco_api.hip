@@ -20,7 +20,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every device array inside the arena.
 struct Layout {
-  size_t D64, Drun, DT, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
+  size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t Wst, t0st, xst, Fst, gst;
   size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work;
   size_t t64, d64, metrics;
@@ -83,17 +83,19 @@ int hip_fail(gmco_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
   } while (0)
 
-size_t dtype_bytes(int dtype) {
-  return (dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64) ? 4 : (dtype == GMCO_DTYPE_BF16 ? 2 : 1);
+bool is_low_precision(int dtype) { return dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8; }
+size_t lp_bytes(int dtype) { return dtype == GMCO_DTYPE_BF16 ? 2 : (dtype == GMCO_DTYPE_FP8 ? 1 : 0); }
+// a run may use the context's dtype and every FP32-operand mode
+bool dtype_available(const int ctx_dtype, int dtype) {
+  return dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64 || dtype == ctx_dtype;
 }
-bool has_transposed(int dtype) { return dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8; }
 
 Dims make_dims(int M, int K, int Pmax, int n_cu) {
   Dims d;
   d.M = M;
   d.K = K;
   d.Kp = round_up(K, kKAlign);
-  d.Mp = round_up(M, kBM);
+  d.Mp = round_up(M, kMAlign);
   d.nblocks = d.Mp / kBM;
   d.Pp = round_up(Pmax, kPT);
   d.ntiles = d.Pp / kPT;
@@ -114,8 +116,9 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   const size_t MK = (size_t)d.Mp * d.Kp;
   const size_t PK = (size_t)d.Pp * d.Kp;
   L.D64 = take(MK * 8);
-  L.Drun = take(MK * dtype_bytes(dtype));
-  L.DT = take(has_transposed(dtype) ? MK * dtype_bytes(dtype) : 0);
+  L.D32 = take(MK * 4);
+  L.Dlp = take(MK * lp_bytes(dtype));
+  L.DTlp = take(is_low_precision(dtype) ? MK * 2 : 0);  // BF16 for the back-projection
   L.colscale = take((size_t)d.Kp * 4);
   L.grp = take((size_t)d.Mp * 4);
   L.perm = take((size_t)d.M * 4);
@@ -147,7 +150,8 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.active = take(2 * sizeof(int));
   L.work = take(sizeof(unsigned long long));
   L.t64 = take(PK * 8);
-  L.d64 = take((size_t)d.Pp * d.Mp * 8);
+  // final doses (Pp x Mp); an FP8 context also widens its matrix (Mp x Kp) here
+  L.d64 = take((size_t)std::max(d.Pp, dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp * 8);
   L.metrics = take((size_t)d.Pp * sizeof(gmco_plan_metrics));
   (void)G;
   L.total = off;
@@ -166,10 +170,10 @@ int copy_h2d(gmco_ctx* c, void* dst, const void* src, size_t bytes) {
   return GMCO_OK;
 }
 
-EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped) {
+EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped, int dtype) {
   EvalArgs a{};
-  a.D = c->at<void>(c->lay.Drun);
-  a.DT = c->at<void>(c->lay.DT);
+  a.D = is_low_precision(dtype) ? c->at<void>(c->lay.Dlp) : c->at<void>(c->lay.D32);
+  a.DT = c->at<void>(c->lay.DTlp);
   a.colscale = c->at<float>(c->lay.colscale);
   a.grp = c->at<int>(c->lay.grp);
   a.x = x;
@@ -369,8 +373,9 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
 
   GMCO_HIP(c, launch_dose_rate(st_dw, cs->point_xyz ? st_pt : nullptr, cs->dose_rate ? st_D : nullptr,
                                c->at<int>(L.perm), M, K, d.Mp, d.Kp, c->at<double>(L.D64), c->stream));
-  GMCO_HIP(c, launch_cast_dose(c->at<double>(L.D64), d.Mp, d.Kp, c->dtype, c->at<void>(L.Drun),
-                               c->at<void>(L.DT), c->at<float>(L.colscale), c->stream));
+  GMCO_HIP(c, launch_cast_dose(c->at<double>(L.D64), d.Mp, d.Kp, c->dtype, c->at<float>(L.D32),
+                               c->at<void>(L.Dlp), c->at<void>(L.DTlp), c->at<float>(L.colscale),
+                               c->stream));
   const int r0 = c->offsets[cs->target_group];
   GMCO_HIP(c, launch_start_time(c->at<double>(L.D64), d.Kp, r0, r0 + counts[cs->target_group], c->rx,
                                 c->at<double>(L.t_bar), c->stream));
@@ -414,7 +419,7 @@ int gmco_evaluate(gmco_ctx* c, const double* x, double* F, double* g) {
   int rc;
   if ((rc = copy_h2d(c, c->at<void>(L.xst), x, (size_t)P * K * 8))) return rc;
   GMCO_HIP(c, launch_x_to_device(c->at<double>(L.xst), P, c->dim.Pp, K, c->dim.Kp, c->at<float>(L.xe), c->stream));
-  EvalArgs a = eval_args(c, c->at<float>(L.xe), false);
+  EvalArgs a = eval_args(c, c->at<float>(L.xe), false, c->dtype);
   GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
   GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, c->at<float>(L.xe), c->dim.S, P, c->dim.Pp, K,
                                  c->dim.Kp, c->at<double>(L.Fst), c->at<double>(L.gst), c->stream));
@@ -430,6 +435,9 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   if (r->max_iter < 0 || !(r->eps >= 0.0) || !(r->c1 > 0.0) || !(r->beta > 0.0 && r->beta < 1.0) ||
       r->max_ls < 1 || r->check_every < 0)
     return fail(c, GMCO_EINVAL, "bad run options");
+  const int dtype = r->dtype < 0 ? c->dtype : r->dtype;
+  if (!dtype_available(c->dtype, dtype))
+    return fail(c, GMCO_EINVAL, "run dtype needs a context created with that dtype");
   GMCO_HIP(c, hipSetDevice(c->device));
   const Layout& L = c->lay;
   const Dims& d = c->dim;
@@ -461,7 +469,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   u.eps = r->eps;
   u.c1 = r->c1;
   u.beta = r->beta;
-  EvalArgs a = eval_args(c, c->at<float>(L.xt), true);
+  EvalArgs a = eval_args(c, c->at<float>(L.xt), true, dtype);
   a.work = work;
   const int check = r->check_every > 0 ? r->check_every : 16;
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
@@ -503,7 +511,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   for (; round < max_rounds; ++round) {
     u.round = (int)round;
     if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
-    GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+    GMCO_HIP(c, launch_eval(a, dtype, c->stream));
     if (r->time_kernels) {
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 1], c->stream));
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 2], c->stream));
@@ -604,17 +612,42 @@ int gmco_get_dose_rate(gmco_ctx* c, double* D64, double* Drun) {
     h64.resize(MK);
     GMCO_HIP(c, hipMemcpyAsync(h64.data(), c->at<void>(c->lay.D64), MK * 8, hipMemcpyDeviceToHost, c->stream));
   }
+  std::vector<uint16_t> hb;
+  std::vector<double> h64w;
   if (Drun) {
-    if (dtype_bytes(c->dtype) != 4) return fail(c, GMCO_EINVAL, "run-dtype export is FP32 only");
-    hr.resize(MK);
-    GMCO_HIP(c, hipMemcpyAsync(hr.data(), c->at<void>(c->lay.Drun), MK * 4, hipMemcpyDeviceToHost, c->stream));
+    if (!is_low_precision(c->dtype)) {
+      hr.resize(MK);
+      GMCO_HIP(c, hipMemcpyAsync(hr.data(), c->at<void>(c->lay.D32), MK * 4, hipMemcpyDeviceToHost, c->stream));
+    } else if (c->dtype == GMCO_DTYPE_BF16) {
+      hb.resize(MK);
+      GMCO_HIP(c, hipMemcpyAsync(hb.data(), c->at<void>(c->lay.Dlp), MK * 2, hipMemcpyDeviceToHost, c->stream));
+    } else {
+      // FP8: widen on the device (hardware encoding) into the FP64 scratch
+      double* wide = c->at<double>(c->lay.d64);
+      GMCO_HIP(c, launch_widen_fp8(c->at<void>(c->lay.Dlp), c->at<float>(c->lay.colscale), d.Mp, d.Kp,
+                                   wide, c->stream));
+      h64w.resize(MK);
+      GMCO_HIP(c, hipMemcpyAsync(h64w.data(), wide, MK * 8, hipMemcpyDeviceToHost, c->stream));
+    }
   }
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < d.M; ++i) {
     const size_t dst = (size_t)c->perm[i] * d.K;
     for (int l = 0; l < d.K; ++l) {
       if (D64) D64[dst + l] = h64[(size_t)i * d.Kp + l];
-      if (Drun) Drun[dst + l] = hr[(size_t)i * d.Kp + l];
+      if (Drun) {
+        if (!hr.empty()) {
+          Drun[dst + l] = hr[(size_t)i * d.Kp + l];
+        } else if (!h64w.empty()) {
+          Drun[dst + l] = h64w[(size_t)i * d.Kp + l];
+        } else {
+          // widen a BF16 bit pattern: its bits are the high half of an FP32
+          const uint32_t bits = (uint32_t)hb[(size_t)i * d.Kp + l] << 16;
+          float f;
+          std::memcpy(&f, &bits, 4);
+          Drun[dst + l] = f;
+        }
+      }
     }
   }
   return GMCO_OK;

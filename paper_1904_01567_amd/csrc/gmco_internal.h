@@ -13,6 +13,7 @@ constexpr int kGmax = GMCO_MAX_GROUPS;
 constexpr int kBM = 16;   // dose points per inner block of the evaluation kernel
 constexpr int kPT = 64;   // plans per workgroup tile of the evaluation kernel
 constexpr int kKAlign = 32;
+constexpr int kMAlign = 32;  // points: a multiple of every kernel's block
 
 // Internal plan states; 0..5 match gmco_plan_status.
 enum : int {
@@ -62,7 +63,7 @@ struct EvalArgs {
   double* Fpart;          // [S][Pp] split-M partial objectives
   unsigned long long* work;  // optional count of workgroups that did not skip
   int Mp, Kp, Pp;
-  int nblocks;            // Mp / kBM
+  int nblocks;            // Mp / kBM (16-point blocks)
   int S;                  // M splits
   int ntiles;             // Pp / kPT
   GroupTable gt;
@@ -90,8 +91,10 @@ struct UpdateArgs {
 hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
                             const int* perm, int M, int K, int Mp, int Kp, double* D64,
                             hipStream_t st);
-hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, void* Drun, void* DT,
-                            float* colscale, hipStream_t st);
+hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, float* D32, void* Dlp,
+                            void* DTlp, float* colscale, hipStream_t st);
+hipError_t launch_widen_fp8(const void* D8, const float* colscale, int Mp, int Kp, double* out,
+                            hipStream_t st);
 hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_end,
                              double prescription, double* t_bar, hipStream_t st);
 hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, const double* t_bar,

@@ -63,11 +63,11 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   constexpr int NF4 = 4 * KP;      // float4 per 16-point block
   constexpr int NPF = (NF4 + 255) / 256;
 
-  __shared__ __attribute__((aligned(16))) float sD[kBM * KS];
+  __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
   __shared__ float sW[kPT * kGmax];
   __shared__ float4 sP[kGmax + 1];
   __shared__ double sP64[kGmax + 1][4];
-  __shared__ int sG[kBM];
+  __shared__ int sG[2][kBM];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -118,112 +118,121 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   const int b_end = (int)(((long long)(s + 1) * a.nblocks) / a.S);
   const f4v* __restrict__ Dg = reinterpret_cast<const f4v*>(a.D);
 
+  // Software pipeline over 16-point blocks with two LDS buffers: while the
+  // dose product of block b runs on one buffer, the back-projection of block
+  // b-1 runs on the other, so the matrix pipe always has independent work.
   f4v pf[NPF];
   int gpre = 0;
-  if (b_begin < b_end) {
-    const f4v* src = Dg + (size_t)b_begin * NF4;
-#pragma unroll
-    for (int i = 0; i < NPF; ++i) {
-      const int idx = tid + 256 * i;
-      if (NF4 % 256 == 0 || idx < NF4) pf[i] = src[idx];
-    }
-    if (tid < kBM) gpre = a.grp[b_begin * kBM + tid];
+#define GMCO_PREFETCH(blk)                                                  \
+  {                                                                         \
+    const f4v* src_ = Dg + (size_t)(blk) * NF4;                             \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
+      const int idx = tid + 256 * i;                                        \
+      if (NF4 % 256 == 0 || idx < NF4) pf[i] = src_[idx];                   \
+    }                                                                       \
+    if (tid < kBM) gpre = a.grp[(blk) * kBM + tid];                         \
+  }
+#define GMCO_STAGE(buf)                                                     \
+  {                                                                         \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
+      const int idx = tid + 256 * i;                                        \
+      if (NF4 % 256 == 0 || idx < NF4) {                                    \
+        const int row = idx / (KP / 4);                                     \
+        const int c4 = idx - row * (KP / 4);                                \
+        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * c4]) = pf[i];     \
+      }                                                                     \
+    }                                                                       \
+    if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
   }
 
-  for (int b = b_begin; b < b_end; ++b) {
+  float phi_prev[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int i = tid; i < kBM * KS; i += 256) sD[1][i] = 0.f;
+  if (b_begin < b_end) GMCO_PREFETCH(b_begin);
+  for (int b = b_begin; b <= b_end; ++b) {
+    const int cur = (b - b_begin) & 1;
+    const int prv = cur ^ 1;
+    // The first iteration back-projects phi_prev = 0 over a zeroed buffer and
+    // the last one repeats a dose product whose result is discarded: both are
+    // harmless and keep the matrix loop free of branches.
+    const bool have_cur = b < b_end;
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NPF; ++i) {
-      const int idx = tid + 256 * i;
-      if (NF4 % 256 == 0 || idx < NF4) {
-        const int row = idx / (KP / 4);
-        const int c4 = idx - row * (KP / 4);
-        *reinterpret_cast<f4v*>(&sD[row * KS + 4 * c4]) = pf[i];
-      }
-    }
-    if (tid < kBM) sG[tid] = gpre;
+    if (have_cur) GMCO_STAGE(cur);
     __syncthreads();
-    {
-      // next block (the last iteration reloads its own block, in bounds)
-      const int bn = (b + 1 < b_end) ? b + 1 : b;
-      const f4v* src = Dg + (size_t)bn * NF4;
-#pragma unroll
-      for (int i = 0; i < NPF; ++i) {
-        const int idx = tid + 256 * i;
-        if (NF4 % 256 == 0 || idx < NF4) pf[i] = src[idx];
-      }
-      if (tid < kBM) gpre = a.grp[bn * kBM + tid];
-    }
+    if (b + 1 < b_end) GMCO_PREFETCH(b + 1);
 
-    // ---- dose product d[16 points][16 plans] and penalty epilogue
-    //      (eq. 1, the bracket of eq. 2, eq. (obj) weights) ----
-    float phi[4];
+    float phi[4] = {0.f, 0.f, 0.f, 0.f};
+    const float* __restrict__ Dc = sD[cur];
+    const float* __restrict__ Dp = sD[prv];
     if constexpr (ACC64) {
       // four independent accumulation chains keep the FP64 pipe busy
       d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
-        const float4 av = *reinterpret_cast<const float4*>(&sD[n * KS + 16 * k + 4 * q]);
+        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
         acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
         acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
         acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
         acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
-      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
-        const int gi = sG[q + 4 * r];
-        const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-        double kap = 0.0, dev = 0.0;
-        if (d < sP64[gi][1]) {
-          dev = d - sP64[gi][1];
-          kap = sP64[gi][0] * dev;
-        } else if (d > sP64[gi][2]) {
-          dev = d - sP64[gi][2];
-          kap = sP64[gi][3] * dev;
+        for (int r = 0; r < 4; ++r)
+          gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * k + n], phi_prev[r], gacc[k]);
+      }
+      if (have_cur) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
+          const int gi = sG[cur][q + 4 * r];
+          const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
+          double kap = 0.0, dev = 0.0;
+          if (d < sP64[gi][1]) {
+            dev = d - sP64[gi][1];
+            kap = sP64[gi][0] * dev;
+          } else if (d > sP64[gi][2]) {
+            dev = d - sP64[gi][2];
+            kap = sP64[gi][3] * dev;
+          }
+          facc += (double)w * (kap * dev);
+          phi[r] = (float)((double)w * kap);
         }
-        facc += (double)w * (kap * dev);
-        phi[r] = (float)((double)w * kap);
       }
     } else {
-      f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+      f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
-        const float4 av = *reinterpret_cast<const float4*>(&sD[n * KS + 16 * k + 4 * q]);
+        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
         acc0 = mfma_f32(av.x, tf[4 * k + 0], acc0);
         acc1 = mfma_f32(av.y, tf[4 * k + 1], acc1);
         acc0 = mfma_f32(av.z, tf[4 * k + 2], acc0);
         acc1 = mfma_f32(av.w, tf[4 * k + 3], acc1);
-      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float d = acc0[r] + acc1[r];
-        const int gi = sG[4 * q + r];
-        const float4 pr = sP[gi];
-        const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-        float kap = 0.f, dev = 0.f;
-        if (d < pr.y) {
-          dev = d - pr.y;
-          kap = pr.x * dev;
-        } else if (d > pr.z) {
-          dev = d - pr.z;
-          kap = pr.w * dev;
+        for (int r = 0; r < 4; ++r)
+          gacc[k] = mfma_f32(Dp[(4 * q + r) * KS + 16 * k + n], phi_prev[r], gacc[k]);
+      }
+      if (have_cur) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = acc0[r] + acc1[r];
+          const int gi = sG[cur][4 * q + r];
+          const float4 pr = sP[gi];
+          const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
+          float kap = 0.f, dev = 0.f;
+          if (d < pr.y) {
+            dev = d - pr.y;
+            kap = pr.x * dev;
+          } else if (d > pr.z) {
+            dev = d - pr.z;
+            kap = pr.w * dev;
+          }
+          facc += (double)(w * (kap * dev));
+          phi[r] = w * kap;
         }
-        facc += (double)(w * (kap * dev));
-        phi[r] = w * kap;
       }
     }
-    // ---- back-projection: G[dwell][plan] += sum_points D[point][dwell] phi ----
 #pragma unroll
-    for (int k = 0; k < NK16; ++k) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = ACC64 ? q + 4 * r : 4 * q + r;
-        const float av = sD[row * KS + 16 * k + n];
-        gacc[k] = mfma_f32(av, phi[r], gacc[k]);
-      }
-    }
+    for (int r = 0; r < 4; ++r) phi_prev[r] = phi[r];
   }
+#undef GMCO_PREFETCH
+#undef GMCO_STAGE
 
   // ---- write split partials ----
   float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
@@ -237,23 +246,391 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
 }
 
+// ---------------------------------------------------------------------------
+// BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16.  Lane l
+// (q = l / 16, n = l % 16) supplies A[n][8q .. 8q+7] and B[8q .. 8q+7][n];
+// accumulator register r holds C[4q + r][n].  Blocks of 32 points: the dose
+// product runs two 16-point row tiles, after which each lane holds the
+// penalty derivative of points {4q..4q+3} and {16+4q..16+4q+3} of its plan,
+// exactly the 8 contraction slots it supplies to the back-projection; the
+// back-projection's A operand (D transposed) is read in that same point
+// order from a dwell-major copy of the tile.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
+__device__ inline f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 template <int KP>
-hipError_t launch_f32_kp(const EvalArgs& a, int dtype, hipStream_t st) {
+__global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
+  constexpr int BMP = 32;              // points per block
+  constexpr int DS = KP + 8;           // D tile row stride (elements): conflict-free b128 reads
+  constexpr int TS = BMP + 4;          // transposed tile row stride: conflict-free b64 reads
+  constexpr int NK32 = KP / 32;        // k-steps of the dose product
+  constexpr int NK16 = KP / 16;        // 16-dwell tiles of the back-projection
+  constexpr int NCH = BMP * KP / 8;    // 16-byte chunks per tile (both tiles)
+  constexpr int NPF = (NCH + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) __bf16 sD[BMP * DS];
+  __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
+  __shared__ float sW[kPT * kGmax];
+  __shared__ float4 sP[kGmax + 1];
+  __shared__ int sG[BMP];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  int s, tile;
+  split_tile(blockIdx.x, a.S, a.ntiles, s, tile);
+  const int p0 = tile * kPT;
+  if (a.ps != nullptr) {
+    int act = 0;
+    if (tid < kPT) act = state_active(a.ps[p0 + tid].status) ? 1 : 0;
+    if (!__syncthreads_or(act)) return;
+  }
+  if (a.work != nullptr && tid == 0) atomicAdd(a.work, 1ull);
+  for (int i = tid; i < kPT * kGmax; i += 256) sW[i] = a.wn[(size_t)p0 * kGmax + i];
+#pragma unroll
+  for (int j = 0; j <= kGmax; ++j)
+    if (tid == j) sP[j] = a.gt.prm[j];
+
+  const int plan = p0 + wave * 16 + n;
+  const float* __restrict__ xrow = a.x + (size_t)plan * KP;
+  // B operand of the dose product: t = x^2 of plan n at dwells 32 k + 8 q + e
+  bf8v tb[NK32];
+#pragma unroll
+  for (int k = 0; k < NK32; ++k) {
+    const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
+    const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
+    tb[k][0] = (__bf16)(x0.x * x0.x);
+    tb[k][1] = (__bf16)(x0.y * x0.y);
+    tb[k][2] = (__bf16)(x0.z * x0.z);
+    tb[k][3] = (__bf16)(x0.w * x0.w);
+    tb[k][4] = (__bf16)(x1.x * x1.x);
+    tb[k][5] = (__bf16)(x1.y * x1.y);
+    tb[k][6] = (__bf16)(x1.z * x1.z);
+    tb[k][7] = (__bf16)(x1.w * x1.w);
+  }
+  f4v gacc[NK16];
+#pragma unroll
+  for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
+  double facc = 0.0;
+
+  const int nb = a.Mp / BMP;
+  const int b_begin = (int)(((long long)s * nb) / a.S);
+  const int b_end = (int)(((long long)(s + 1) * nb) / a.S);
+  const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
+  const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
+
+  u4v pd[NPF], pt[NPF];
+  int gpre = 0;
+#define GMCO_PF16(blk)                                                          \
+  {                                                                             \
+    const u4v* srcd = Dg + (size_t)(blk) * NCH;                                 \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                           \
+      const int c = tid + 256 * i;                                              \
+      if (NCH % 256 == 0 || c < NCH) {                                          \
+        pd[i] = srcd[c];                                                        \
+        const int l = c >> 2, part = c & 3;                                    \
+        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp +          \
+                                                (size_t)(blk) * BMP + part * 8); \
+      }                                                                         \
+    }                                                                           \
+    if (tid < BMP) gpre = a.grp[(blk) * BMP + tid];                             \
+  }
+  if (b_begin < b_end) GMCO_PF16(b_begin);
+
+  for (int b = b_begin; b < b_end; ++b) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int c = tid + 256 * i;
+      if (NCH % 256 == 0 || c < NCH) {
+        const int row = c / (KP / 8), c8 = c - row * (KP / 8);
+        *reinterpret_cast<u4v*>(&sD[row * DS + 8 * c8]) = pd[i];
+        const int l = c >> 2, part = c & 3;
+        u2v* dst = reinterpret_cast<u2v*>(&sT[l * TS + part * 8]);
+        dst[0] = u2v{pt[i][0], pt[i][1]};
+        dst[1] = u2v{pt[i][2], pt[i][3]};
+      }
+    }
+    if (tid < BMP) sG[tid] = gpre;
+    __syncthreads();
+    {
+      const int bn = (b + 1 < b_end) ? b + 1 : b;
+      GMCO_PF16(bn);
+    }
+
+    // ---- dose product for the two 16-point row tiles ----
+    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int k = 0; k < NK32; ++k) {
+      const bf8v a0 = *reinterpret_cast<const bf8v*>(&sD[n * DS + 32 * k + 8 * q]);
+      const bf8v a1 = *reinterpret_cast<const bf8v*>(&sD[(16 + n) * DS + 32 * k + 8 * q]);
+      acc0 = mfma_bf16(a0, tb[k], acc0);
+      acc1 = mfma_bf16(a1, tb[k], acc1);
+    }
+    // ---- penalty epilogue ----
+    bf8v phi;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float d = e < 4 ? acc0[e] : acc1[e - 4];
+      const int pt_ = e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4);
+      const int gi = sG[pt_];
+      const float4 pr = sP[gi];
+      const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
+      float kap = 0.f, dev = 0.f;
+      if (d < pr.y) {
+        dev = d - pr.y;
+        kap = pr.x * dev;
+      } else if (d > pr.z) {
+        dev = d - pr.z;
+        kap = pr.w * dev;
+      }
+      facc += (double)(w * (kap * dev));
+      phi[e] = (__bf16)(w * kap);
+    }
+    // ---- back-projection over the 32 points ----
+#pragma unroll
+    for (int k = 0; k < NK16; ++k) {
+      const bf4v lo = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 4 * q]);
+      const bf4v hi = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 16 + 4 * q]);
+      const bf8v av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      gacc[k] = mfma_bf16(av, phi, gacc[k]);
+    }
+  }
+#undef GMCO_PF16
+
+  float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
+#pragma unroll
+  for (int k = 0; k < NK16; ++k) {
+    *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
+        make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  }
+  facc += __shfl_xor(facc, 16);
+  facc += __shfl_xor(facc, 32);
+  if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
+}
+
+// ---------------------------------------------------------------------------
+// FP8 dose product (e4m3, v_mfma_f32_16x16x32_fp8_fp8, same lane layout as the
+// BF16 op with 8 one-byte elements per lane): D is stored as D_il / s_l with
+// one scale per dwell column (s_l = max_i D_il / 224), the dwell times enter
+// as t_l s_l / u_p with one scale per plan (u_p = max_l t_l s_l / 224), and
+// d = u_p * sum.  The back-projection runs in BF16 on the BF16 transposed
+// copy of D, as in the BF16 kernel.  Both conversions use the hardware's own
+// FP8 encoding, so the format convention never enters the arithmetic.
+// ---------------------------------------------------------------------------
+__device__ inline f4v mfma_fp8(long a, long b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+__device__ inline unsigned pack_fp8x4(float a, float b, float c, float d) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
+  constexpr int BMP = 32;
+  constexpr int DS = KP + 8;           // FP8 tile row stride (bytes): conflict-free b64 reads
+  constexpr int TS = BMP + 4;          // BF16 transposed tile row stride (elements)
+  constexpr int NK32 = KP / 32;
+  constexpr int NK16 = KP / 16;
+  constexpr int NCH8 = BMP * KP / 16;  // 16-byte chunks of the FP8 tile
+  constexpr int NCH = BMP * KP / 8;    // 16-byte chunks of the BF16 transposed tile
+  constexpr int NPF8 = (NCH8 + 255) / 256;
+  constexpr int NPF = (NCH + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) unsigned char sD[BMP * DS];
+  __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
+  __shared__ float sW[kPT * kGmax];
+  __shared__ float4 sP[kGmax + 1];
+  __shared__ int sG[BMP];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  int s, tile;
+  split_tile(blockIdx.x, a.S, a.ntiles, s, tile);
+  const int p0 = tile * kPT;
+  if (a.ps != nullptr) {
+    int act = 0;
+    if (tid < kPT) act = state_active(a.ps[p0 + tid].status) ? 1 : 0;
+    if (!__syncthreads_or(act)) return;
+  }
+  if (a.work != nullptr && tid == 0) atomicAdd(a.work, 1ull);
+  for (int i = tid; i < kPT * kGmax; i += 256) sW[i] = a.wn[(size_t)p0 * kGmax + i];
+#pragma unroll
+  for (int j = 0; j <= kGmax; ++j)
+    if (tid == j) sP[j] = a.gt.prm[j];
+
+  const int plan = p0 + wave * 16 + n;
+  const float* __restrict__ xrow = a.x + (size_t)plan * KP;
+  // scaled dwell times t_l s_l, their per-plan maximum, then FP8 and BF16 fragments
+  float ts[NK32][8];
+  float tmax = 0.f;
+#pragma unroll
+  for (int k = 0; k < NK32; ++k) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int l = 32 * k + 8 * q + e;
+      const float xv = xrow[l];
+      ts[k][e] = xv * xv * a.colscale[l];
+      tmax = fmaxf(tmax, ts[k][e]);
+    }
+  }
+  tmax = fmaxf(tmax, __shfl_xor(tmax, 16));
+  tmax = fmaxf(tmax, __shfl_xor(tmax, 32));
+  const float u = tmax > 0.f ? tmax / 224.f : 1.f;
+  const float inv_u = 1.f / u;
+  long tb[NK32];
+#pragma unroll
+  for (int k = 0; k < NK32; ++k) {
+    const unsigned lo = pack_fp8x4(ts[k][0] * inv_u, ts[k][1] * inv_u, ts[k][2] * inv_u, ts[k][3] * inv_u);
+    const unsigned hi = pack_fp8x4(ts[k][4] * inv_u, ts[k][5] * inv_u, ts[k][6] * inv_u, ts[k][7] * inv_u);
+    tb[k] = (long)(((unsigned long)hi << 32) | lo);
+  }
+  f4v gacc[NK16];
+#pragma unroll
+  for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
+  double facc = 0.0;
+
+  const int nb = a.Mp / BMP;
+  const int b_begin = (int)(((long long)s * nb) / a.S);
+  const int b_end = (int)(((long long)(s + 1) * nb) / a.S);
+  const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
+  const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
+
+  u4v pd[NPF8], pt[NPF];
+  int gpre = 0;
+#define GMCO_PF8(blk)                                                           \
+  {                                                                             \
+    const u4v* srcd = Dg + (size_t)(blk) * NCH8;                                \
+    _Pragma("unroll") for (int i = 0; i < NPF8; ++i) {                          \
+      const int c = tid + 256 * i;                                              \
+      if (NCH8 % 256 == 0 || c < NCH8) pd[i] = srcd[c];                         \
+    }                                                                           \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                           \
+      const int c = tid + 256 * i;                                              \
+      if (NCH % 256 == 0 || c < NCH) {                                          \
+        const int l = c >> 2, part = c & 3;                                     \
+        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp +          \
+                                              (size_t)(blk) * BMP + part * 8);  \
+      }                                                                         \
+    }                                                                           \
+    if (tid < BMP) gpre = a.grp[(blk) * BMP + tid];                             \
+  }
+  if (b_begin < b_end) GMCO_PF8(b_begin);
+
+  for (int b = b_begin; b < b_end; ++b) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NPF8; ++i) {
+      const int c = tid + 256 * i;
+      if (NCH8 % 256 == 0 || c < NCH8) {
+        const int row = c / (KP / 16), c16 = c - row * (KP / 16);
+        u2v* dst = reinterpret_cast<u2v*>(&sD[row * DS + 16 * c16]);
+        dst[0] = u2v{pd[i][0], pd[i][1]};
+        dst[1] = u2v{pd[i][2], pd[i][3]};
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int c = tid + 256 * i;
+      if (NCH % 256 == 0 || c < NCH) {
+        const int l = c >> 2, part = c & 3;
+        u2v* dst = reinterpret_cast<u2v*>(&sT[l * TS + part * 8]);
+        dst[0] = u2v{pt[i][0], pt[i][1]};
+        dst[1] = u2v{pt[i][2], pt[i][3]};
+      }
+    }
+    if (tid < BMP) sG[tid] = gpre;
+    __syncthreads();
+    {
+      const int bn = (b + 1 < b_end) ? b + 1 : b;
+      GMCO_PF8(bn);
+    }
+
+    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int k = 0; k < NK32; ++k) {
+      const long a0 = *reinterpret_cast<const long*>(&sD[n * DS + 32 * k + 8 * q]);
+      const long a1 = *reinterpret_cast<const long*>(&sD[(16 + n) * DS + 32 * k + 8 * q]);
+      acc0 = mfma_fp8(a0, tb[k], acc0);
+      acc1 = mfma_fp8(a1, tb[k], acc1);
+    }
+    bf8v phi;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float d = u * (e < 4 ? acc0[e] : acc1[e - 4]);
+      const int pt_ = e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4);
+      const int gi = sG[pt_];
+      const float4 pr = sP[gi];
+      const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
+      float kap = 0.f, dev = 0.f;
+      if (d < pr.y) {
+        dev = d - pr.y;
+        kap = pr.x * dev;
+      } else if (d > pr.z) {
+        dev = d - pr.z;
+        kap = pr.w * dev;
+      }
+      facc += (double)(w * (kap * dev));
+      phi[e] = (__bf16)(w * kap);
+    }
+#pragma unroll
+    for (int k = 0; k < NK16; ++k) {
+      const bf4v lo = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 4 * q]);
+      const bf4v hi = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 16 + 4 * q]);
+      const bf8v av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      gacc[k] = mfma_bf16(av, phi, gacc[k]);
+    }
+  }
+#undef GMCO_PF8
+
+  float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
+#pragma unroll
+  for (int k = 0; k < NK16; ++k) {
+    *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
+        make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  }
+  facc += __shfl_xor(facc, 16);
+  facc += __shfl_xor(facc, 32);
+  if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
+}
+
+template <int KP>
+hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
+  const dim3 grid(a.S * a.ntiles), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_f32<KP, true>), dim3(a.S * a.ntiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_eval_f32<KP, true>), grid, block, 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32)
+    hipLaunchKernelGGL((k_eval_f32<KP, false>), grid, block, 0, st, a);
+  else if (dtype == GMCO_DTYPE_BF16)
+    hipLaunchKernelGGL((k_eval_bf16<KP>), grid, block, 0, st, a);
+  else if (dtype == GMCO_DTYPE_FP8)
+    hipLaunchKernelGGL((k_eval_fp8<KP>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL((k_eval_f32<KP, false>), dim3(a.S * a.ntiles), dim3(256), 0, st, a);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st) {
-  if (dtype != GMCO_DTYPE_F32 && dtype != GMCO_DTYPE_F32_ACC64) return hipErrorInvalidValue;
   switch (a.Kp) {
 #define GMCO_KP_CASE(v) \
   case v:               \
-    return launch_f32_kp<v>(a, dtype, st);
+    return launch_kp<v>(a, dtype, st);
     GMCO_KP_CASE(32)
     GMCO_KP_CASE(64)
     GMCO_KP_CASE(96)

@@ -31,10 +31,11 @@ __device__ inline double dot(const float (&a)[E], const float (&b)[E]) {
   return wave_sum((double)s);
 }
 
-template <int E>
+// MH = register capacity for history pairs (MH >= m).  The pairs are held in
+// registers in age order (0 = newest) so every loop index is a compile-time
+// constant; all their loads are issued together before the recursion.
+template <int E, int MH>
 __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
-  // two-loop coefficients of each wave's plan (uniform across the wave)
-  __shared__ double sAl[4][GMCO_MAX_HISTORY];
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.active_count[(a.round + 1) & 1] = 0;
@@ -43,32 +44,49 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
   if (!state_active(st.status)) return;
 
   const int Kp = a.Kp;
+  const int m = a.m;
   const size_t row = (size_t)p * Kp;
   bool valid[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) valid[j] = (lane + 64 * j) < Kp;
 
   // ---- objective and gradient at the evaluated point ----
-  double Ft = 0.0;
-  for (int s = 0; s < a.S; ++s) Ft += a.Fpart[(size_t)s * a.Pp + p];
-  float xt[E], gt[E];
+  float xt[E], gt[E], x[E], g[E], d[E];
+  float G[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    xt[j] = 0.f;
-    gt[j] = 0.f;
-    if (valid[j]) {
-      const int e = lane + 64 * j;
-      float G = 0.f;
-      for (int s = 0; s < a.S; ++s) G += a.Gpart[((size_t)s * a.Pp + p) * Kp + e];
-      xt[j] = a.xt[row + e];
-      gt[j] = 4.f * xt[j] * G;
+    G[j] = 0.f;
+    const int e = lane + 64 * j;
+    xt[j] = valid[j] ? a.xt[row + e] : 0.f;
+    x[j] = valid[j] ? a.x[row + e] : 0.f;
+    g[j] = valid[j] ? a.g[row + e] : 0.f;
+    d[j] = valid[j] ? a.dir[row + e] : 0.f;
+  }
+  for (int s0 = 0; s0 < a.S; s0 += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = s0 + u;
+      if (s < a.S) {
+        const float* src = a.Gpart + ((size_t)s * a.Pp + p) * Kp;
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+          if (valid[j]) G[j] += src[lane + 64 * j];
+      }
     }
   }
+  // split partials of F: one load per lane, then a fixed-order wave sum
+  double fpart = 0.0;
+  for (int s = lane; s < a.S; s += 64) fpart += a.Fpart[(size_t)s * a.Pp + p];
+  const double Ft = wave_sum(fpart);
+#pragma unroll
+  for (int j = 0; j < E; ++j) gt[j] = 4.f * xt[j] * G[j];
   st.nevals += 1;
 
-  float x[E], g[E], d[E];
   bool need_dir = false;
   bool stop = false;
+  bool pushed = false;
+  float sv[E], yv[E];
+  double rho_new = 0.0;
   if (st.status == ST_INIT) {
     // take the evaluated point as the current iterate (start or resume)
     const double gg = dot(gt, gt);
@@ -76,7 +94,6 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
     for (int j = 0; j < E; ++j) {
       x[j] = xt[j];
       g[j] = gt[j];
-      d[j] = 0.f;
       if (valid[j]) {
         a.x[row + lane + 64 * j] = x[j];
         a.g[row + lane + 64 * j] = g[j];
@@ -97,15 +114,8 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       need_dir = true;
     }
   } else {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      x[j] = valid[j] ? a.x[row + lane + 64 * j] : 0.f;
-      g[j] = valid[j] ? a.g[row + lane + 64 * j] : 0.f;
-      d[j] = valid[j] ? a.dir[row + lane + 64 * j] : 0.f;
-    }
     const bool accept = isfinite(Ft) && (Ft <= st.F + a.c1 * st.alpha * st.gtp);
     if (accept) {
-      float sv[E], yv[E];
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         sv[j] = xt[j] - x[j];
@@ -116,17 +126,19 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       const double yy = dot(yv, yv);
       if (sy > 1e-10 * sqrt(ss * yy)) {
         const int slot = st.hhead;
-        float* Sd = a.Sh + ((size_t)p * a.m + slot) * Kp;
-        float* Yd = a.Yh + ((size_t)p * a.m + slot) * Kp;
+        float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
+        float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
 #pragma unroll
         for (int j = 0; j < E; ++j)
           if (valid[j]) {
             Sd[lane + 64 * j] = sv[j];
             Yd[lane + 64 * j] = yv[j];
           }
-        if (lane == 0) a.rho[(size_t)p * a.m + slot] = 1.0 / sy;
-        st.hhead = (slot + 1) % a.m;
-        st.hcount = min(st.hcount + 1, a.m);
+        rho_new = 1.0 / sy;
+        if (lane == 0) a.rho[(size_t)p * m + slot] = rho_new;
+        st.hhead = (slot + 1) % m;
+        st.hcount = min(st.hcount + 1, m);
+        pushed = true;
       }
       st.Fprev = st.F;
       st.F = Ft;
@@ -171,62 +183,72 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       stop = true;
     } else {
       double alpha0 = 1.0;
-      if (st.hcount == 0) {
+      const int hc = st.hcount;
+      if (hc == 0) {
 #pragma unroll
         for (int j = 0; j < E; ++j) d[j] = -g[j];
         alpha0 = 1.0 / sqrt(gg);
       } else {
-        // two-loop recursion, newest pair first
+        // history in age order; the pair pushed this round comes from registers
+        float hs[MH][E], hy[MH][E];
+        double hr[MH];
+#pragma unroll
+        for (int i = 0; i < MH; ++i) {
+          hr[i] = 0.0;
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            hs[i][j] = 0.f;
+            hy[i][j] = 0.f;
+          }
+          if (i < hc) {
+            if (i == 0 && pushed) {
+              hr[0] = rho_new;
+#pragma unroll
+              for (int j = 0; j < E; ++j) {
+                hs[0][j] = sv[j];
+                hy[0][j] = yv[j];
+              }
+            } else {
+              const int slot = (st.hhead - 1 - i + 2 * m) % m;
+              const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
+              const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
+              hr[i] = a.rho[(size_t)p * m + slot];
+#pragma unroll
+              for (int j = 0; j < E; ++j)
+                if (valid[j]) {
+                  hs[i][j] = Sd[lane + 64 * j];
+                  hy[i][j] = Yd[lane + 64 * j];
+                }
+            }
+          }
+        }
+        // two-loop recursion: newest to oldest, scale, oldest to newest
         float qv[E];
 #pragma unroll
         for (int j = 0; j < E; ++j) qv[j] = g[j];
-        double* al = sAl[threadIdx.x >> 6];
-        const int newest = (st.hhead - 1 + a.m) % a.m;
-        for (int i = 0; i < st.hcount; ++i) {
-          const int slot = (st.hhead - 1 - i + 2 * a.m) % a.m;
-          const float* Sd = a.Sh + ((size_t)p * a.m + slot) * Kp;
-          const float* Yd = a.Yh + ((size_t)p * a.m + slot) * Kp;
-          float sv[E], yv[E];
+        double al[MH];
 #pragma unroll
-          for (int j = 0; j < E; ++j) {
-            sv[j] = valid[j] ? Sd[lane + 64 * j] : 0.f;
-            yv[j] = valid[j] ? Yd[lane + 64 * j] : 0.f;
+        for (int i = 0; i < MH; ++i) {
+          al[i] = 0.0;
+          if (i < hc) {
+            al[i] = hr[i] * dot(hs[i], qv);
+            const float af = (float)al[i];
+#pragma unroll
+            for (int j = 0; j < E; ++j) qv[j] = fmaf(-af, hy[i][j], qv[j]);
           }
-          const double ai = a.rho[(size_t)p * a.m + slot] * dot(sv, qv);
-          al[i] = ai;
-          const float af = (float)ai;
-#pragma unroll
-          for (int j = 0; j < E; ++j) qv[j] = fmaf(-af, yv[j], qv[j]);
         }
-        double gamma;
-        {
-          const float* Sd = a.Sh + ((size_t)p * a.m + newest) * Kp;
-          const float* Yd = a.Yh + ((size_t)p * a.m + newest) * Kp;
-          float sv[E], yv[E];
-#pragma unroll
-          for (int j = 0; j < E; ++j) {
-            sv[j] = valid[j] ? Sd[lane + 64 * j] : 0.f;
-            yv[j] = valid[j] ? Yd[lane + 64 * j] : 0.f;
-          }
-          gamma = dot(sv, yv) / dot(yv, yv);
-        }
+        const double gamma = dot(hs[0], hy[0]) / dot(hy[0], hy[0]);
         const float gf = (float)gamma;
 #pragma unroll
         for (int j = 0; j < E; ++j) qv[j] *= gf;
-        for (int i = st.hcount - 1; i >= 0; --i) {
-          const int slot = (st.hhead - 1 - i + 2 * a.m) % a.m;
-          const float* Sd = a.Sh + ((size_t)p * a.m + slot) * Kp;
-          const float* Yd = a.Yh + ((size_t)p * a.m + slot) * Kp;
-          float sv[E], yv[E];
 #pragma unroll
-          for (int j = 0; j < E; ++j) {
-            sv[j] = valid[j] ? Sd[lane + 64 * j] : 0.f;
-            yv[j] = valid[j] ? Yd[lane + 64 * j] : 0.f;
+        for (int i = MH - 1; i >= 0; --i) {
+          if (i < hc) {
+            const double bi = hr[i] * dot(hy[i], qv);
+            const float cf = (float)(al[i] - bi);
+#pragma unroll
+            for (int j = 0; j < E; ++j) qv[j] = fmaf(cf, hs[i][j], qv[j]);
           }
-          const double bi = a.rho[(size_t)p * a.m + slot] * dot(yv, qv);
-          const float cf = (float)(al[i] - bi);
-#pragma unroll
-          for (int j = 0; j < E; ++j) qv[j] = fmaf(cf, sv[j], qv[j]);
         }
 #pragma unroll
         for (int j = 0; j < E; ++j) d[j] = -qv[j];
@@ -266,7 +288,11 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
 
 template <int E>
 hipError_t launch_update_e(const UpdateArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_update<E>, dim3((a.Pp + 3) / 4), dim3(256), 0, st, a);
+  const dim3 grid((a.Pp + 3) / 4), block(256);
+  if (a.m <= 4) hipLaunchKernelGGL((k_update<E, 4>), grid, block, 0, st, a);
+  else if (a.m <= 10) hipLaunchKernelGGL((k_update<E, 10>), grid, block, 0, st, a);
+  else if (a.m <= 16) hipLaunchKernelGGL((k_update<E, 16>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((k_update<E, GMCO_MAX_HISTORY>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 

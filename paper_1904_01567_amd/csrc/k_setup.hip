@@ -37,6 +37,69 @@ __global__ void k_cast_f32(const double* __restrict__ D64, size_t n, float* __re
     out[idx] = (float)D64[idx];
 }
 
+// Round an FP32 value to BF16, nearest with ties to even (finite inputs).
+__device__ inline uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// BF16 copies of the dose-rate matrix, row-major (points x dwells) for the
+// dose product and dwell-major for the back-projection.
+__global__ void k_cast_bf16(const double* __restrict__ D64, int Mp, int Kp,
+                            uint16_t* __restrict__ D, uint16_t* __restrict__ DT) {
+  const size_t n = (size_t)Mp * Kp;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / Kp, l = idx - i * Kp;
+    const uint16_t v = bf16_rne((float)D64[idx]);
+    D[idx] = v;
+    DT[l * Mp + i] = v;
+  }
+}
+
+// Per-dwell-column scale for the FP8 copy: s_l = max_i D_il / 224 (1 for an
+// all-zero column), one workgroup per column, fixed reduction order.
+__global__ void k_colscale(const double* __restrict__ D64, int Mp, int Kp, float* __restrict__ cs) {
+  __shared__ double red[256];
+  const int l = blockIdx.x;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < Mp; i += blockDim.x) m = fmax(m, fabs(D64[(size_t)i * Kp + l]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cs[l] = red[0] > 0.0 ? (float)(red[0] / 224.0) : 1.f;
+}
+
+// FP8 (hardware e4m3 encoding) copy of D_il / s_l, row-major, and the BF16
+// dwell-major copy for the back-projection.
+__global__ void k_cast_fp8(const double* __restrict__ D64, int Mp, int Kp,
+                           const float* __restrict__ cs, unsigned char* __restrict__ D8,
+                           uint16_t* __restrict__ DT) {
+  const size_t n = (size_t)Mp * Kp;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / Kp, l = idx - i * Kp;
+    const float v = (float)D64[idx];
+    D8[idx] = (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(v / cs[l], 0.f, 0, false) & 0xff);
+    DT[l * Mp + i] = bf16_rne(v);
+  }
+}
+
+// FP8 bytes widened to double with the column scale applied (for export).
+__global__ void k_widen_fp8(const unsigned char* __restrict__ D8, const float* __restrict__ cs,
+                            int Mp, int Kp, double* __restrict__ out) {
+  const size_t n = (size_t)Mp * Kp;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t l = idx % Kp;
+    out[idx] = (double)__builtin_amdgcn_cvt_f32_fp8((int)D8[idx], 0) * (double)cs[l];
+  }
+}
+
 // t_bar = Rx / mean over the target rows of sum_l D_il, one workgroup, fixed
 // summation order.
 __global__ void k_start_time(const double* __restrict__ D64, int Kp, int r0, int r1, double rx,
@@ -124,16 +187,34 @@ hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const
   return hipGetLastError();
 }
 
-hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, void* Drun, void* DT,
-                            float* colscale, hipStream_t st) {
-  (void)DT;
+hipError_t launch_cast_dose(const double* D64, int Mp, int Kp, int dtype, float* D32, void* Dlp,
+                            void* DTlp, float* colscale, hipStream_t st) {
   (void)colscale;
   const size_t n = (size_t)Mp * Kp;
-  if (dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64) {
-    hipLaunchKernelGGL(k_cast_f32, dim3(1024), dim3(256), 0, st, D64, n, (float*)Drun);
+  hipLaunchKernelGGL(k_cast_f32, dim3(1024), dim3(256), 0, st, D64, n, D32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (dtype == GMCO_DTYPE_BF16) {
+    hipLaunchKernelGGL(k_cast_bf16, dim3(1024), dim3(256), 0, st, D64, Mp, Kp, (uint16_t*)Dlp,
+                       (uint16_t*)DTlp);
     return hipGetLastError();
   }
-  return hipErrorInvalidValue;
+  if (dtype == GMCO_DTYPE_FP8) {
+    hipLaunchKernelGGL(k_colscale, dim3(Kp), dim3(256), 0, st, D64, Mp, Kp, colscale);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cast_fp8, dim3(1024), dim3(256), 0, st, D64, Mp, Kp, colscale,
+                       (unsigned char*)Dlp, (uint16_t*)DTlp);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_widen_fp8(const void* D8, const float* colscale, int Mp, int Kp, double* out,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_widen_fp8, dim3(1024), dim3(256), 0, st, (const unsigned char*)D8,
+                     colscale, Mp, Kp, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_end,

@@ -41,6 +41,16 @@ def test_dose_rate_matrix_c1():
     np.testing.assert_allclose(Dg, D, rtol=4e-16 * 8, atol=0)
     Dr = pl.dose_rate(run_dtype=True)
     np.testing.assert_array_equal(Dr, Dg.astype(np.float32).astype(np.float64))
+    import torch
+    pb = planner(c, W, dtype="bf16")
+    Db = pb.dose_rate(run_dtype=True)
+    ref_bf16 = torch.tensor(D, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    np.testing.assert_array_equal(Db, ref_bf16)
+    p8 = planner(c, W, dtype="fp8")
+    D8 = p8.dose_rate(run_dtype=True)
+    # e4m3 rounding of D / s_l: relative error at most 2^-4 (normal range)
+    big = D > 1e-3 * D.max(axis=0, keepdims=True)
+    assert np.max(np.abs(D8 - D)[big] / D[big]) <= 2.0 ** -4 + 1e-6
     tb = O.uniform_start_time(D, c.group, 15.0)
     assert pl.start_time() == pytest.approx(tb, rel=1e-13)
 
@@ -59,6 +69,16 @@ def test_user_dose_rate_matrix_is_used_as_given():
 # ---------------------------------------------------------------------------
 # a1-a4: one fused evaluation of F and dF/dx
 # ---------------------------------------------------------------------------
+# Bounds per arithmetic: FP32 rounding of D and t (6e-8 relative) and FP32
+# accumulation give a few 1e-7 on F; BF16 rounds D, t and the penalty
+# derivative to 8 significant bits (relative 2^-9 = 2e-3 each), which moves a
+# dose near 15 Gy by ~1e-3 relative and the penalty of points near a band edge
+# by up to a few percent.
+# FP8 e4m3 keeps 3 significant bits (relative 2^-4 per element) on D and the
+# scaled dwell times; the back-projection stays BF16.
+TOL = {"f32": (2e-5, 2e-4), "f32acc64": (2e-5, 2e-4), "bf16": (5e-2, 5e-2), "fp8": (0.5, 0.5)}
+
+
 def _check_eval(c, D, W, x, tag, dtype="f32"):
     pl = planner(c, W, dtype=dtype)
     F, g = pl.evaluate(x)
@@ -66,12 +86,13 @@ def _check_eval(c, D, W, x, tag, dtype="f32"):
     relF = float(np.max(np.abs(F - Fr) / Fr))
     relg = _rel_grad_err(g, gr)
     announce(f"{tag}: max rel F err {relF:.2e}, max grad err / scale {relg:.2e}")
-    assert relF <= 2e-5
-    assert relg <= 2e-4
+    tf, tg = TOL[dtype]
+    assert relF <= tf
+    assert relg <= tg
     return pl
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f32acc64"])
+@pytest.mark.parametrize("dtype", ["f32", "f32acc64", "bf16", "fp8"])
 def test_evaluate_c1_random_points(dtype):
     announce(f"evaluate C1 {dtype}")
     c, D = oracle_dose_rate("case_c1")
@@ -87,7 +108,7 @@ def test_evaluate_c1_random_points(dtype):
     ((611, 101, 150, 145), 5, 7, 70),  # ragged: M = 1007, K = 35, two plan tiles
     ((2000, 400, 700, 741), 17, 29, 130),  # K = 493 -> Kp = 512, three tiles
 ])
-@pytest.mark.parametrize("dtype", ["f32", "f32acc64"])
+@pytest.mark.parametrize("dtype", ["f32", "f32acc64", "bf16", "fp8"])
 def test_evaluate_ragged_shapes(M_pts, n_cath, n_dw, P, dtype):
     announce(f"evaluate ragged {M_pts} {n_cath}x{n_dw} P={P} {dtype}")
     c = cases.make_case(n_cath, n_dw, M_pts, seed=sum(M_pts))
@@ -98,7 +119,7 @@ def test_evaluate_ragged_shapes(M_pts, n_cath, n_dw, P, dtype):
     _check_eval(c, D, W, x, f"M={c.M} K={c.K} P={P} {dtype}", dtype)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f32acc64"])
+@pytest.mark.parametrize("dtype", ["f32", "f32acc64", "bf16", "fp8"])
 def test_evaluate_c2_sampled_plans(dtype):
     # Full size (20,000 points x 360 dwells x 1,000 plans) in the launch shape
     # the benchmark times; the oracle checks a sample of plans one by one.
@@ -113,9 +134,10 @@ def test_evaluate_c2_sampled_plans(dtype):
     Fr, gr = O.objective_and_gradient_x(D, x[sample], c.group, PARAMS, W[sample])
     relF = float(np.max(np.abs(F[sample] - Fr) / Fr))
     relg = _rel_grad_err(g[sample], gr)
-    announce(f"C2 sampled: rel F {relF:.2e}, grad {relg:.2e}")
-    assert relF <= 2e-5
-    assert relg <= 2e-4
+    announce(f"C2 sampled {dtype}: rel F {relF:.2e}, grad {relg:.2e}")
+    tf, tg = TOL[dtype]
+    assert relF <= tf
+    assert relg <= tg
     assert np.all(np.isfinite(F)) and np.all(np.isfinite(g))
 
 
@@ -170,13 +192,14 @@ def test_objective_decreases_every_accepted_step():
         prev = F
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32acc64", 1e-4), ("f32", 3e-4)])
+@pytest.mark.parametrize("dtype,tol", [("f32acc64", 1e-4), ("f32", 3e-4), ("bf16", 0.5)])
 def test_c1_reaches_the_oracle_optimum(dtype, tol):
     # End to end: every plan within tol of the oracle's optimum F* (FP64
     # re-evaluation on the device) and target V100 within 0.1 percentage point.
     # FP32 accumulation of the dose leaves objective noise of ~1e-6 relative
     # that stalls the line search at a relative excess near 1e-4; the FP64-
-    # accumulated dose removes it.
+    # accumulated dose removes it.  BF16 rounding of the dwell times stalls it
+    # at 1e-2 .. 3e-1: BF16 only serves as the first stage of a ladder.
     announce(f"C1 end to end {dtype}")
     c, D = oracle_dose_rate("case_c1")
     W = cases.weights_c1()
@@ -194,6 +217,26 @@ def test_c1_reaches_the_oracle_optimum(dtype, tol):
     assert np.all(rel >= -1e-6)
     if dtype == "f32acc64":
         assert np.all(np.abs(dv) <= 0.1 + 1e-9)
+
+
+def test_precision_ladder_reaches_the_oracle_optimum():
+    # BF16 for the first iterations, then the FP64-accumulated dose product on
+    # the same L-BFGS state (plans stalled by BF16 noise resume).
+    announce("C1 ladder bf16 -> f32acc64")
+    c, D = oracle_dose_rate("case_c1")
+    W = cases.weights_c1()
+    x0 = O.default_start(D, c.group, 15.0, W.shape[0])
+    ref = O.optimize(D, c.group, PARAMS, W, x0, O.LbfgsOptions(max_iter=6000, eps=1e-15))
+    pl = planner(c, W, dtype="bf16")
+    i1 = pl.optimize(max_iter=150, dtype="bf16")
+    m1 = pl.metrics()
+    i2 = pl.optimize(max_iter=3000, dtype="f32acc64", resume_stopped=True)
+    m = pl.metrics()
+    rel1 = (m1["F64"] - ref["F"]) / ref["F"]
+    rel = (m["F64"] - ref["F"]) / ref["F"]
+    announce(f"ladder: after bf16 max rel {rel1.max():.2e} ({i1['rounds']} rounds); "
+             f"final max rel {rel.max():.2e} ({i2['rounds']} rounds)")
+    assert np.all(rel <= 1e-4) and np.all(rel >= -1e-6)
 
 
 def test_metrics_match_oracle_at_given_times():
