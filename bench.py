@@ -34,13 +34,15 @@ TOL_V100 = 0.1      # target V100 difference in percentage points
 # Accepted L-BFGS steps per plan after which every checked plan of the
 # workload meets both tolerances (calibrated with --calibrate against the
 # oracle optima in tests/golden/c2_reference_optima.json).
-ITERS = {"f32acc64": 2000, "f32": 2000}
+ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
 # MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
 PEAK_F64 = 78.6
 PEAK_F32 = 157.3
 
 
-DTYPE_NAMES = {"f32acc64": "f32 operands, f64-accumulated dose", "f32": "f32", "bf16": "bf16"}
+DTYPE_NAMES = {"f32acc64": "f32 operands, f64-accumulated dose",
+               "f32chunk64": "f32 matrix ops, 16-dwell partials accumulated in f64",
+               "f32": "f32", "bf16": "bf16"}
 PEAK_BF16 = 2500.0
 
 
@@ -53,7 +55,7 @@ def eval_peak_tflops(dtype: str) -> float:
         return 2.0 / (1.0 / PEAK_F64 + 1.0 / PEAK_F32)
     if dtype == "bf16":
         return PEAK_BF16
-    return PEAK_F32
+    return PEAK_F32        # f32 and f32chunk64 run both products on FP32 matrix ops
 
 
 def golden_path():
@@ -113,7 +115,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32", "bf16"])
+    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32chunk64", "f32", "bf16"])
     ap.add_argument("--ladder", type=str, default=None,
                     help="precision ladder, e.g. bf16:150,f32acc64:2000 (iteration caps are "
                          "cumulative); the context is created with the first dtype")

@@ -49,12 +49,17 @@ typedef enum {
  *   F32_ACC64  FP32 operands; the dose accumulated and the penalty evaluated
  *              in FP64 (FP32 accumulation of the dose leaves noise in the
  *              objective that stalls the line search near the optimum);
- *              FP32 back-projection. */
+ *              FP32 back-projection.
+ *   F32_CHUNK64 FP32 matrix ops sum 16 dwells at a time; these partial doses
+ *              are accumulated and the penalty evaluated in FP64; FP32
+ *              back-projection.  Near F32 speed, objective noise far below
+ *              the FP32 mode's. */
 typedef enum {
   GMCO_DTYPE_F32 = 0,
   GMCO_DTYPE_BF16 = 1,
   GMCO_DTYPE_FP8 = 2,
-  GMCO_DTYPE_F32_ACC64 = 3
+  GMCO_DTYPE_F32_ACC64 = 3,
+  GMCO_DTYPE_F32_CHUNK64 = 4
 } gmco_dtype;
 
 /* Per-plan status. */

@@ -16,7 +16,7 @@ GMCO_MAX_GROUPS = 8
 GMCO_MAX_HISTORY = 32
 GMCO_MAX_DWELLS = 512
 
-DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "f32acc64": 3}
+DTYPES = {"f32": 0, "bf16": 1, "fp8": 2, "f32acc64": 3, "f32chunk64": 4}
 STATUS_NAMES = {0: "running", 1: "converged", 2: "maxiter", 3: "ls_fail",
                 4: "nonfinite", 5: "inactive"}
 ERRORS = {0: "GMCO_OK", -1: "GMCO_EINVAL", -2: "GMCO_ENOMEM", -3: "GMCO_EHIP",

@@ -87,7 +87,8 @@ bool is_low_precision(int dtype) { return dtype == GMCO_DTYPE_BF16 || dtype == G
 size_t lp_bytes(int dtype) { return dtype == GMCO_DTYPE_BF16 ? 2 : (dtype == GMCO_DTYPE_FP8 ? 1 : 0); }
 // a run may use the context's dtype and every FP32-operand mode
 bool dtype_available(const int ctx_dtype, int dtype) {
-  return dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64 || dtype == ctx_dtype;
+  return dtype == GMCO_DTYPE_F32 || dtype == GMCO_DTYPE_F32_ACC64 ||
+         dtype == GMCO_DTYPE_F32_CHUNK64 || dtype == ctx_dtype;
 }
 
 Dims make_dims(int M, int K, int Pmax, int n_cu) {
@@ -213,7 +214,7 @@ const char* gmco_last_error(const gmco_ctx* c) { return c ? c->err.c_str() : "nu
 int gmco_create(gmco_ctx** out, const gmco_opts* o) {
   if (!out || !o) return GMCO_EINVAL;
   *out = nullptr;
-  if (o->dtype < GMCO_DTYPE_F32 || o->dtype > GMCO_DTYPE_F32_ACC64) return GMCO_EINVAL;
+  if (o->dtype < GMCO_DTYPE_F32 || o->dtype > GMCO_DTYPE_F32_CHUNK64) return GMCO_EINVAL;
   if (o->history < 1 || o->history > GMCO_MAX_HISTORY) return GMCO_EINVAL;
   if (o->max_plans < 1 || o->max_plans > (1 << 20)) return GMCO_EINVAL;
   int ndev = 0;

@@ -52,12 +52,18 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
   }
 }
 
-// ACC64 = false: FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4_f32).
-// ACC64 = true : FP32 operands, the dose accumulated in FP64
-//                (v_mfma_f64_16x16x4_f64) and the penalty evaluated in FP64;
-//                the back-projection stays FP32.
-template <int KP, bool ACC64>
+// MODE_F32    : FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4_f32).
+// MODE_ACC64  : FP32 operands, the dose accumulated in FP64
+//               (v_mfma_f64_16x16x4_f64) and the penalty evaluated in FP64.
+// MODE_CHUNK64: FP32 matrix ops sum 16 dwells at a time from zero; those
+//               partial doses are accumulated in FP64 on the vector ALU and
+//               the penalty is evaluated in FP64.
+// The back-projection is FP32 in all three.
+enum { MODE_F32 = 0, MODE_ACC64 = 1, MODE_CHUNK64 = 2 };
+
+template <int KP, int MODE>
 __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
+  constexpr bool ACC64 = MODE == MODE_ACC64;
   constexpr int KS = KP + 4;       // LDS row stride (floats): conflict-free both ways
   constexpr int NK16 = KP / 16;    // 16-dwell slices
   constexpr int NF4 = 4 * KP;      // float4 per 16-point block
@@ -148,6 +154,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   float phi_prev[4] = {0.f, 0.f, 0.f, 0.f};
   for (int i = tid; i < kBM * KS; i += 256) sD[1][i] = 0.f;
   if (b_begin < b_end) GMCO_PREFETCH(b_begin);
+#pragma unroll 1
   for (int b = b_begin; b <= b_end; ++b) {
     const int cur = (b - b_begin) & 1;
     const int prv = cur ^ 1;
@@ -182,6 +189,42 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
         for (int r = 0; r < 4; ++r) {
           const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
           const int gi = sG[cur][q + 4 * r];
+          const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
+          double kap = 0.0, dev = 0.0;
+          if (d < sP64[gi][1]) {
+            dev = d - sP64[gi][1];
+            kap = sP64[gi][0] * dev;
+          } else if (d > sP64[gi][2]) {
+            dev = d - sP64[gi][2];
+            kap = sP64[gi][3] * dev;
+          }
+          facc += (double)w * (kap * dev);
+          phi[r] = (float)((double)w * kap);
+        }
+      }
+    } else if constexpr (MODE == MODE_CHUNK64) {
+      const f4v z = {0.f, 0.f, 0.f, 0.f};
+      double ds[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < NK16; ++k) {
+        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
+        // one 16-dwell partial per slice, interleaved with the back-projection
+        f4v c0 = mfma_f32(av.x, tf[4 * k + 0], z);
+        gacc[k] = mfma_f32(Dp[(4 * q + 0) * KS + 16 * k + n], phi_prev[0], gacc[k]);
+        c0 = mfma_f32(av.y, tf[4 * k + 1], c0);
+        gacc[k] = mfma_f32(Dp[(4 * q + 1) * KS + 16 * k + n], phi_prev[1], gacc[k]);
+        c0 = mfma_f32(av.z, tf[4 * k + 2], c0);
+        gacc[k] = mfma_f32(Dp[(4 * q + 2) * KS + 16 * k + n], phi_prev[2], gacc[k]);
+        c0 = mfma_f32(av.w, tf[4 * k + 3], c0);
+        gacc[k] = mfma_f32(Dp[(4 * q + 3) * KS + 16 * k + n], phi_prev[3], gacc[k]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ds[r] += (double)c0[r];
+      }
+      if (have_cur) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double d = ds[r];
+          const int gi = sG[cur][4 * q + r];
           const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
           double kap = 0.0, dev = 0.0;
           if (d < sP64[gi][1]) {
@@ -612,9 +655,11 @@ template <int KP>
 hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   const dim3 grid(a.S * a.ntiles), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_f32<KP, true>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_eval_f32<KP, MODE_ACC64>), grid, block, 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32_CHUNK64)
+    hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
-    hipLaunchKernelGGL((k_eval_f32<KP, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_eval_f32<KP, MODE_F32>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_BF16)
     hipLaunchKernelGGL((k_eval_bf16<KP>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_FP8)
