@@ -221,3 +221,36 @@ def case_batch(index: int) -> Case:
 def small_case(K_cath=4, n_dwell=4, n_points=(60, 20, 25, 25), seed=3) -> Case:
     """A tiny case for brute-force and unit checks."""
     return make_case(K_cath, n_dwell, n_points, seed=seed)
+
+
+def case_learned(index: int) -> Case:
+    """Cases for the learned warm start: the paper-scale layout (18 x 20 = 360
+    dwells, 20,000 points 50/10/20/20) with semi-axes jittered by +-20 %."""
+    return make_case(18, 20, (10000, 2000, 4000, 4000), seed=5000 + index, jitter=0.2)
+
+
+def weights_learned(index: int, n_plans: int = 1000) -> np.ndarray:
+    return hidden_weights(n_plans, seed=6000 + index)
+
+
+def mlp_init(sizes, seed: int) -> np.ndarray:
+    """Seeded He-uniform initial parameters of a fully connected network,
+    flat: for each layer W (n_out x n_in, row-major) then b (zeros)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k in range(len(sizes) - 1):
+        n_in, n_out = sizes[k], sizes[k + 1]
+        lim = math.sqrt(6.0 / n_in)
+        parts.append(rng.uniform(-lim, lim, size=n_out * n_in))
+        parts.append(np.zeros(n_out))
+    return np.concatenate(parts)
+
+
+def batch_order(n_samples: int, n_steps: int, batch: int, seed: int) -> np.ndarray:
+    """(n_steps * batch,) int32 sample indices: consecutive seeded shuffles."""
+    rng = np.random.default_rng(seed)
+    out = []
+    need = n_steps * batch
+    while sum(len(o) for o in out) < need:
+        out.append(rng.permutation(n_samples))
+    return np.concatenate(out)[:need].astype(np.int32)

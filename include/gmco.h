@@ -223,8 +223,47 @@ int gmco_get_dose_rate(gmco_ctx* ctx, double* D64, double* Drun);
 /* Default start time t_bar of the loaded case. */
 int gmco_get_start_time(gmco_ctx* ctx, double* t_bar);
 
+/* Case features of the learned warm start: for every structure j, the
+ * histogram over dwells of the distance from the dwell to the nearest point
+ * of j, in 16 bins of 0.25 cm (the last bin open-ended), divided by the dwell
+ * count.  out has n_groups x 16 floats.  Needs a case loaded with point
+ * positions.  (Project extension; not in the paper.) */
+int gmco_case_features(gmco_ctx* ctx, float* out);
+
 const char* gmco_last_error(const gmco_ctx* ctx);
 const char* gmco_strerror(int status);
+
+/* ---- Learned warm start: a fully connected ReLU network (project
+ * extension, not in the paper) trained on plans the method produced, mapping
+ * hidden weights and case features to start dwell weights.  Products run on
+ * BF16 matrix ops with FP32 accumulation; loss, gradients and Adam state are
+ * FP32.  Parameter layout: for each layer W (n_out x n_in, row-major) then b
+ * (n_out); hidden layers ReLU, output linear; loss = mean squared error over
+ * all outputs of a batch. ---- */
+typedef struct gmco_mlp gmco_mlp;
+
+/* sizes = (n_in, hidden..., n_out), n_sizes >= 2, each 1..4096; max_batch
+ * rows per forward pass.  Parameters start at zero; set them with
+ * gmco_mlp_set_params.  Errors: EINVAL, ENOLIB, ENOMEM. */
+int gmco_mlp_create(gmco_mlp** out, int device, const int* sizes, int n_sizes, int max_batch);
+int gmco_mlp_destroy(gmco_mlp* net);
+int gmco_mlp_set_stream(gmco_mlp* net, void* stream);
+int gmco_mlp_param_count(const gmco_mlp* net, size_t* n);
+/* Copy n parameters in (resets the Adam moments) or out. */
+int gmco_mlp_set_params(gmco_mlp* net, const float* params, size_t n);
+int gmco_mlp_get_params(gmco_mlp* net, float* params, size_t n);
+/* Loss and gradient of one batch of B rows (host arrays X: B x n_in, Y: B x
+ * n_out); grad (n parameters) may be NULL. */
+int gmco_mlp_loss_grad(gmco_mlp* net, int B, const float* X, const float* Y, double* loss, float* grad);
+/* Copy a training set of N rows to the device (replaces an earlier one). */
+int gmco_mlp_set_data(gmco_mlp* net, int N, const float* X, const float* Y);
+/* n_steps Adam steps (beta 0.9 / 0.999, eps 1e-8) on batches of B rows whose
+ * indices into the training set are order[s * B .. s * B + B - 1]; the mean
+ * batch loss is returned.  Errors: EINVAL, ESTATE (no data), EHIP. */
+int gmco_mlp_train(gmco_mlp* net, int n_steps, int B, const int32_t* order, float lr, double* mean_loss);
+/* Y (B x n_out) = network(X (B x n_in)); any B, processed in max_batch chunks. */
+int gmco_mlp_predict(gmco_mlp* net, int B, const float* X, float* Y);
+const char* gmco_mlp_last_error(const gmco_mlp* net);
 
 #ifdef __cplusplus
 }

@@ -5,8 +5,8 @@ for gfx950 behind the C-ABI of include/gmco.h.
 There is no CPU fallback: without the built library (libgmco.so) and a
 gfx950 GPU every call raises.
 """
-from ._binding import (DTYPES, EXPORTS, GmcoError, Planner, STATUS_NAMES,  # noqa: F401
-                       load_library, LIB_PATH)
+from ._binding import (DTYPES, EXPORTS, GmcoError, Network, Planner,  # noqa: F401
+                       STATUS_NAMES, load_library, LIB_PATH)
 
-__all__ = ["Planner", "GmcoError", "load_library", "DTYPES", "STATUS_NAMES", "EXPORTS",
-           "LIB_PATH"]
+__all__ = ["Planner", "Network", "GmcoError", "load_library", "DTYPES", "STATUS_NAMES",
+           "EXPORTS", "LIB_PATH"]

@@ -27,7 +27,10 @@ EXPORTS = (
     "gmco_create", "gmco_destroy", "gmco_set_stream", "gmco_workspace_bytes",
     "gmco_bind_workspace", "gmco_load_case", "gmco_set_weights", "gmco_evaluate",
     "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
-    "gmco_get_dose_rate", "gmco_get_start_time", "gmco_last_error", "gmco_strerror",
+    "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_last_error",
+    "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
+    "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
+    "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
 )
 
 
@@ -105,12 +108,26 @@ def load_library(path: Optional[str] = None):
     lib.gmco_get_metrics.argtypes = [vp, C.POINTER(gmco_plan_metrics)]
     lib.gmco_get_dose_rate.argtypes = [vp, dp, dp]
     lib.gmco_get_start_time.argtypes = [vp, dp]
+    lib.gmco_case_features.argtypes = [vp, C.POINTER(C.c_float)]
+    fp = C.POINTER(C.c_float)
+    lib.gmco_mlp_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int]
+    lib.gmco_mlp_destroy.argtypes = [vp]
+    lib.gmco_mlp_set_stream.argtypes = [vp, vp]
+    lib.gmco_mlp_param_count.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.gmco_mlp_set_params.argtypes = [vp, fp, C.c_size_t]
+    lib.gmco_mlp_get_params.argtypes = [vp, fp, C.c_size_t]
+    lib.gmco_mlp_loss_grad.argtypes = [vp, C.c_int, fp, fp, dp, fp]
+    lib.gmco_mlp_set_data.argtypes = [vp, C.c_int, fp, fp]
+    lib.gmco_mlp_train.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_float, dp]
+    lib.gmco_mlp_predict.argtypes = [vp, C.c_int, fp, fp]
+    lib.gmco_mlp_last_error.argtypes = [vp]
+    lib.gmco_mlp_last_error.restype = C.c_char_p
     lib.gmco_last_error.argtypes = [vp]
     lib.gmco_last_error.restype = C.c_char_p
     lib.gmco_strerror.argtypes = [C.c_int]
     lib.gmco_strerror.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("gmco_last_error", "gmco_strerror"):
+        if name not in ("gmco_last_error", "gmco_strerror", "gmco_mlp_last_error"):
             getattr(lib, name).restype = C.c_int
     if path is None:
         _lib = lib
@@ -277,7 +294,99 @@ class Planner:
             self._check(self.lib.gmco_get_dose_rate(self._ctx, _dptr(D), None), "get_dose_rate")
         return D
 
+    def case_features(self) -> np.ndarray:
+        out = np.empty(self.G * 16, dtype=np.float32)
+        self._check(self.lib.gmco_case_features(self._ctx, out.ctypes.data_as(C.POINTER(C.c_float))),
+                    "case_features")
+        return out
+
     def start_time(self) -> float:
         v = C.c_double()
         self._check(self.lib.gmco_get_start_time(self._ctx, C.byref(v)), "get_start_time")
         return float(v.value)
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _f32(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None and out.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {out.shape}")
+    return out
+
+
+class Network:
+    """The learned warm start's network on the GPU (gmco_mlp_*)."""
+
+    def __init__(self, sizes, max_batch: int = 1024, device: int = 0, use_torch: bool = True):
+        self.lib = load_library()
+        self._net = C.c_void_p()
+        self.sizes = [int(v) for v in sizes]
+        arr = (C.c_int * len(self.sizes))(*self.sizes)
+        rc = self.lib.gmco_mlp_create(C.byref(self._net), device, arr, len(self.sizes), int(max_batch))
+        if rc != 0:
+            raise GmcoError(rc, "mlp_create: " + self.lib.gmco_strerror(rc).decode())
+        self.max_batch = int(max_batch)
+        if use_torch:
+            import torch
+            self._check(self.lib.gmco_mlp_set_stream(
+                self._net, C.c_void_p(torch.cuda.current_stream(device).cuda_stream)), "set_stream")
+        n = C.c_size_t()
+        self._check(self.lib.gmco_mlp_param_count(self._net, C.byref(n)), "param_count")
+        self.n_params = int(n.value)
+
+    def _check(self, rc, what):
+        if rc != 0:
+            m = self.lib.gmco_mlp_last_error(self._net) if self._net else b""
+            raise GmcoError(rc, f"{what}: {(m or b'').decode() or self.lib.gmco_strerror(rc).decode()}")
+
+    def close(self):
+        if self._net:
+            self.lib.gmco_mlp_destroy(self._net)
+            self._net = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = _f32(p, (self.n_params,))
+        self._check(self.lib.gmco_mlp_set_params(self._net, _fptr(p), p.size), "set_params")
+
+    def params(self) -> np.ndarray:
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.gmco_mlp_get_params(self._net, _fptr(p), p.size), "get_params")
+        return p
+
+    def loss_grad(self, X, Y):
+        X = _f32(X)
+        Y = _f32(Y)
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.gmco_mlp_loss_grad(self._net, X.shape[0], _fptr(X), _fptr(Y),
+                                                C.byref(loss), _fptr(g)), "loss_grad")
+        return float(loss.value), g
+
+    def set_data(self, X, Y):
+        X = _f32(X)
+        Y = _f32(Y)
+        self._check(self.lib.gmco_mlp_set_data(self._net, X.shape[0], _fptr(X), _fptr(Y)), "set_data")
+
+    def train(self, order, batch: int, lr: float) -> float:
+        order = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+        steps = order.size // batch
+        loss = C.c_double()
+        self._check(self.lib.gmco_mlp_train(self._net, steps, batch,
+                                            order.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            float(lr), C.byref(loss)), "train")
+        return float(loss.value)
+
+    def predict(self, X) -> np.ndarray:
+        X = _f32(X)
+        Y = np.empty((X.shape[0], self.sizes[-1]), dtype=np.float32)
+        self._check(self.lib.gmco_mlp_predict(self._net, X.shape[0], _fptr(X), _fptr(Y)), "predict")
+        return Y

@@ -23,7 +23,7 @@ struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t Wst, t0st, xst, Fst, gst;
   size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work;
-  size_t t64, d64, metrics;
+  size_t t64, d64, metrics, hist, feat;
   size_t total;
 };
 
@@ -55,6 +55,7 @@ struct gmco_ctx {
   int target = 0;
   std::vector<int> counts, offsets, perm;  // host copies
   bool case_loaded = false;
+  bool has_points = false;  // point positions were given (features need them)
   int P = 0;              // current batch, 0 = none
   int* host_count = nullptr;  // pinned mirror of the active counter
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -154,6 +155,8 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   // final doses (Pp x Mp); an FP8 context also widens its matrix (Mp x Kp) here
   L.d64 = take((size_t)std::max(d.Pp, dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp * 8);
   L.metrics = take((size_t)d.Pp * sizeof(gmco_plan_metrics));
+  L.hist = take(kGmax * 16 * 4);
+  L.feat = take(kGmax * 16 * 4);
   (void)G;
   L.total = off;
   return L;
@@ -381,6 +384,7 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   GMCO_HIP(c, launch_start_time(c->at<double>(L.D64), d.Kp, r0, r0 + counts[cs->target_group], c->rx,
                                 c->at<double>(L.t_bar), c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  c->has_points = cs->point_xyz != nullptr;
   c->case_loaded = true;
   return GMCO_OK;
 }
@@ -651,6 +655,23 @@ int gmco_get_dose_rate(gmco_ctx* c, double* D64, double* Drun) {
       }
     }
   }
+  return GMCO_OK;
+}
+
+int gmco_case_features(gmco_ctx* c, float* out) {
+  if (!c || !out) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  if (!c->has_points) return fail(c, GMCO_EINVAL, "features need point positions");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  double* stage = c->at<double>(L.stage);
+  const double* dw = stage + (size_t)d.M * d.K;
+  const double* pts = dw + (size_t)d.K * 3;
+  GMCO_HIP(c, launch_features(dw, pts, c->at<int>(L.perm), c->at<int>(L.goff), c->at<int>(L.gcnt), d.K,
+                              c->G, c->at<unsigned>(L.hist), c->at<float>(L.feat), c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(out, c->at<void>(L.feat), (size_t)c->G * 16 * 4, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
   return GMCO_OK;
 }
 

@@ -118,4 +118,7 @@ hipError_t launch_metrics(const double* d64, const double* W64, const PlanState*
                           const double* volume_cc, double prescription, gmco_plan_metrics* out,
                           hipStream_t st);
 
+hipError_t launch_features(const double* dwell, const double* pts, const int* perm, const int* goff,
+                           const int* gcnt, int K, int G, unsigned* hist, float* out, hipStream_t st);
+
 }  // namespace gmco
