@@ -203,6 +203,25 @@ int gmco_evaluate(gmco_ctx* ctx, const double* x, double* F, double* g);
  * ENUMERIC (every plan non-finite at its start). */
 int gmco_optimize(gmco_ctx* ctx, const gmco_run* run, gmco_run_info* info);
 
+/* Batched uneven cases: run the same options on n contexts (one case and
+ * weight batch each, one device) in lockstep rounds on the first context's
+ * stream.  rounds_per_graph > 0 captures that many rounds (rounded up to even)
+ * of every case into one HIP graph and replays it until every plan of every
+ * case has stopped; 0 issues plain launches.  infos has n entries (NULL
+ * allowed); device_ms is the whole batch's time.  Plans that stop early keep
+ * skipping their share on the device.  Errors as gmco_optimize. */
+int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_run_info* infos,
+                       int rounds_per_graph);
+
+/* Autotuner: time the evaluation kernel of this case and batch for each
+ * candidate split count of the point range (workgroups per plan tile; up to
+ * 32) and keep the fastest.  reps timed launches per candidate on the
+ * context stream.  Needs a weight batch.  best_split / best_us may be NULL. */
+int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* best_us);
+
+/* Set the split count directly (e.g. from a cache of autotuned shapes). */
+int gmco_set_split(gmco_ctx* ctx, int split);
+
 /* t = x^2 of every plan, P x K, FP64 (computed on the device). */
 int gmco_get_dwell_times(gmco_ctx* ctx, double* t);
 

@@ -6,7 +6,7 @@ There is no CPU fallback: without the built library (libgmco.so) and a
 gfx950 GPU every call raises.
 """
 from ._binding import (DTYPES, EXPORTS, GmcoError, Network, Planner,  # noqa: F401
-                       STATUS_NAMES, load_library, LIB_PATH)
+                       STATUS_NAMES, load_library, LIB_PATH, optimize_many)
 
 __all__ = ["Planner", "Network", "GmcoError", "load_library", "DTYPES", "STATUS_NAMES",
-           "EXPORTS", "LIB_PATH"]
+           "EXPORTS", "LIB_PATH", "optimize_many"]

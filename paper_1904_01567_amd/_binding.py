@@ -27,7 +27,8 @@ EXPORTS = (
     "gmco_create", "gmco_destroy", "gmco_set_stream", "gmco_workspace_bytes",
     "gmco_bind_workspace", "gmco_load_case", "gmco_set_weights", "gmco_evaluate",
     "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
-    "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_last_error",
+    "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_optimize_many",
+    "gmco_autotune", "gmco_set_split", "gmco_last_error",
     "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
     "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
     "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
@@ -109,6 +110,10 @@ def load_library(path: Optional[str] = None):
     lib.gmco_get_dose_rate.argtypes = [vp, dp, dp]
     lib.gmco_get_start_time.argtypes = [vp, dp]
     lib.gmco_case_features.argtypes = [vp, C.POINTER(C.c_float)]
+    lib.gmco_optimize_many.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(gmco_run),
+                                       C.POINTER(gmco_run_info), C.c_int]
+    lib.gmco_autotune.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_float)]
+    lib.gmco_set_split.argtypes = [vp, C.c_int]
     fp = C.POINTER(C.c_float)
     lib.gmco_mlp_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int]
     lib.gmco_mlp_destroy.argtypes = [vp]
@@ -294,6 +299,16 @@ class Planner:
             self._check(self.lib.gmco_get_dose_rate(self._ctx, _dptr(D), None), "get_dose_rate")
         return D
 
+    def autotune(self, dtype: Optional[str] = None, reps: int = 5):
+        best = C.c_int()
+        us = C.c_float()
+        self._check(self.lib.gmco_autotune(self._ctx, -1 if dtype is None else DTYPES[dtype], reps,
+                                           C.byref(best), C.byref(us)), "autotune")
+        return int(best.value), float(us.value)
+
+    def set_split(self, split: int):
+        self._check(self.lib.gmco_set_split(self._ctx, int(split)), "set_split")
+
     def case_features(self) -> np.ndarray:
         out = np.empty(self.G * 16, dtype=np.float32)
         self._check(self.lib.gmco_case_features(self._ctx, out.ctypes.data_as(C.POINTER(C.c_float))),
@@ -304,6 +319,23 @@ class Planner:
         v = C.c_double()
         self._check(self.lib.gmco_get_start_time(self._ctx, C.byref(v)), "get_start_time")
         return float(v.value)
+
+
+def optimize_many(planners, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
+                  max_ls: int = 30, check_every: int = 16, rounds_per_graph: int = 16,
+                  resume_stopped: bool = False, dtype: Optional[str] = None):
+    """Lockstep batched L-BFGS over several cases (gmco_optimize_many)."""
+    lib = load_library()
+    n = len(planners)
+    arr = (C.c_void_p * n)(*[p._ctx.value for p in planners])
+    r = gmco_run(int(max_iter), float(eps), float(c1), float(beta), int(max_ls), int(check_every),
+                 0, int(bool(resume_stopped)), -1 if dtype is None else DTYPES[dtype], 0)
+    infos = (gmco_run_info * n)()
+    rc = lib.gmco_optimize_many(arr, n, C.byref(r), infos, int(rounds_per_graph))
+    if rc != 0:
+        msgs = [lib.gmco_last_error(p._ctx).decode() for p in planners]
+        raise GmcoError(rc, "optimize_many: " + "; ".join(m for m in msgs if m))
+    return [{k: getattr(i, k) for k, _ in gmco_run_info._fields_} for i in infos]
 
 
 def _fptr(a: np.ndarray):

@@ -29,7 +29,10 @@ struct Layout {
 
 struct Dims {
   int M = 0, K = 0, Mp = 0, Kp = 0, Pp = 0, S = 1, ntiles = 1, nblocks = 0;
+  int S_cap = 1;  // split counts up to this fit the partial buffers (autotuning range)
 };
+
+constexpr int kSplitTuneMax = 32;
 
 }  // namespace
 
@@ -59,6 +62,8 @@ struct gmco_ctx {
   int P = 0;              // current batch, 0 = none
   int* host_count = nullptr;  // pinned mirror of the active counter
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t gstream = nullptr;  // library-owned stream for graph capture
+  hipEvent_t gev = nullptr;
   GroupTable gt{};
 
   template <class T>
@@ -104,6 +109,7 @@ Dims make_dims(int M, int K, int Pmax, int n_cu) {
   int S = std::max(1, n_cu / d.ntiles);
   if (S >= 8) S -= S % 8;
   d.S = std::max(1, std::min(S, d.nblocks));
+  d.S_cap = std::max(d.S, std::min(kSplitTuneMax, d.nblocks));
   return d;
 }
 
@@ -147,8 +153,8 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.Yh = take(PK * m * 4);
   L.rho = take((size_t)d.Pp * m * 8);
   L.ps = take((size_t)d.Pp * sizeof(PlanState));
-  L.Gpart = take((size_t)d.S * PK * 4);
-  L.Fpart = take((size_t)d.S * d.Pp * 8);
+  L.Gpart = take((size_t)d.S_cap * PK * 4);
+  L.Fpart = take((size_t)d.S_cap * d.Pp * 8);
   L.active = take(2 * sizeof(int));
   L.work = take(sizeof(unsigned long long));
   L.t64 = take(PK * 8);
@@ -193,6 +199,68 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped, int dty
   a.ntiles = c->dim.ntiles;
   a.gt = c->gt;
   return a;
+}
+
+UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  UpdateArgs u{};
+  u.Gpart = c->at<float>(L.Gpart);
+  u.Fpart = c->at<double>(L.Fpart);
+  u.x = c->at<float>(L.x);
+  u.g = c->at<float>(L.g);
+  u.dir = c->at<float>(L.dir);
+  u.xt = c->at<float>(L.xt);
+  u.Sh = c->at<float>(L.Sh);
+  u.Yh = c->at<float>(L.Yh);
+  u.rho = c->at<double>(L.rho);
+  u.ps = c->at<PlanState>(L.ps);
+  u.active_count = c->at<int>(L.active);
+  u.Kp = d.Kp;
+  u.Pp = d.Pp;
+  u.S = d.S;
+  u.m = c->m;
+  u.K = d.K;
+  u.max_iter = r->max_iter;
+  u.max_ls = r->max_ls;
+  u.eps = r->eps;
+  u.c1 = r->c1;
+  u.beta = r->beta;
+  return u;
+}
+
+int check_run(gmco_ctx* c, const gmco_run* r, int* dtype) {
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  if (r->max_iter < 0 || !(r->eps >= 0.0) || !(r->c1 > 0.0) || !(r->beta > 0.0 && r->beta < 1.0) ||
+      r->max_ls < 1 || r->check_every < 0)
+    return fail(c, GMCO_EINVAL, "bad run options");
+  *dtype = r->dtype < 0 ? c->dtype : r->dtype;
+  if (!dtype_available(c->dtype, *dtype))
+    return fail(c, GMCO_EINVAL, "run dtype needs a context created with that dtype");
+  return GMCO_OK;
+}
+
+int summarize(gmco_ctx* c, long long rounds, float ms, double eval_ms, double update_ms,
+              unsigned long long work, gmco_run_info* info) {
+  std::vector<PlanState> ps(c->P);
+  GMCO_HIP(c, hipMemcpy(ps.data(), c->at<void>(c->lay.ps), (size_t)c->P * sizeof(PlanState), hipMemcpyDeviceToHost));
+  gmco_run_info inf{};
+  inf.rounds = (int)rounds;
+  for (const PlanState& s : ps) {
+    inf.n_converged += s.status == ST_CONVERGED;
+    inf.n_maxiter += s.status == ST_MAXITER;
+    inf.n_ls_fail += s.status == ST_LSFAIL;
+    inf.n_nonfinite += s.status == ST_NONFINITE;
+    inf.max_iters = std::max(inf.max_iters, s.iter);
+  }
+  inf.device_ms = ms;
+  inf.eval_ms = (float)eval_ms;
+  inf.update_ms = (float)update_ms;
+  inf.eval_launches = (int)rounds;
+  inf.eval_work = (double)work / (double)(c->dim.S * c->dim.ntiles);
+  if (info) *info = inf;
+  if (inf.n_nonfinite == c->P) return fail(c, GMCO_ENUMERIC, "every plan has a non-finite objective");
+  return GMCO_OK;
 }
 
 }  // namespace
@@ -252,6 +320,8 @@ int gmco_destroy(gmco_ctx* c) {
   if (c->host_count) hipHostFree(c->host_count);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->gev) hipEventDestroy(c->gev);
+  if (c->gstream) hipStreamDestroy(c->gstream);
   delete c;
   return GMCO_OK;
 }
@@ -436,13 +506,9 @@ int gmco_evaluate(gmco_ctx* c, const double* x, double* F, double* g) {
 
 int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   if (!c || !r) return GMCO_EINVAL;
-  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
-  if (r->max_iter < 0 || !(r->eps >= 0.0) || !(r->c1 > 0.0) || !(r->beta > 0.0 && r->beta < 1.0) ||
-      r->max_ls < 1 || r->check_every < 0)
-    return fail(c, GMCO_EINVAL, "bad run options");
-  const int dtype = r->dtype < 0 ? c->dtype : r->dtype;
-  if (!dtype_available(c->dtype, dtype))
-    return fail(c, GMCO_EINVAL, "run dtype needs a context created with that dtype");
+  int dtype = 0;
+  int rc = check_run(c, r, &dtype);
+  if (rc) return rc;
   GMCO_HIP(c, hipSetDevice(c->device));
   const Layout& L = c->lay;
   const Dims& d = c->dim;
@@ -452,28 +518,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   GMCO_HIP(c, hipMemsetAsync(work, 0, sizeof(unsigned long long), c->stream));
   GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), d.Pp, d.Kp,
                             r->max_iter, r->resume_stopped, c->stream));
-  UpdateArgs u{};
-  u.Gpart = c->at<float>(L.Gpart);
-  u.Fpart = c->at<double>(L.Fpart);
-  u.x = c->at<float>(L.x);
-  u.g = c->at<float>(L.g);
-  u.dir = c->at<float>(L.dir);
-  u.xt = c->at<float>(L.xt);
-  u.Sh = c->at<float>(L.Sh);
-  u.Yh = c->at<float>(L.Yh);
-  u.rho = c->at<double>(L.rho);
-  u.ps = c->at<PlanState>(L.ps);
-  u.active_count = active;
-  u.Kp = d.Kp;
-  u.Pp = d.Pp;
-  u.S = d.S;
-  u.m = c->m;
-  u.K = d.K;
-  u.max_iter = r->max_iter;
-  u.max_ls = r->max_ls;
-  u.eps = r->eps;
-  u.c1 = r->c1;
-  u.beta = r->beta;
+  UpdateArgs u = update_args(c, r);
   EvalArgs a = eval_args(c, c->at<float>(L.xt), true, dtype);
   a.work = work;
   const int check = r->check_every > 0 ? r->check_every : 16;
@@ -540,26 +585,165 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   if (r->time_kernels) GMCO_HIP(c, harvest(in_block));
   unsigned long long done = 0;
   GMCO_HIP(c, hipMemcpy(&done, work, sizeof(done), hipMemcpyDeviceToHost));
-  std::vector<PlanState> ps(c->P);
-  GMCO_HIP(c, hipMemcpy(ps.data(), c->at<void>(L.ps), (size_t)c->P * sizeof(PlanState), hipMemcpyDeviceToHost));
-  gmco_run_info inf{};
-  inf.rounds = (int)round;
-  for (const PlanState& s : ps) {
-    inf.n_converged += s.status == ST_CONVERGED;
-    inf.n_maxiter += s.status == ST_MAXITER;
-    inf.n_ls_fail += s.status == ST_LSFAIL;
-    inf.n_nonfinite += s.status == ST_NONFINITE;
-    inf.max_iters = std::max(inf.max_iters, s.iter);
-  }
   float ms = 0.f;
   GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  inf.device_ms = ms;
-  inf.eval_ms = (float)eval_ms;
-  inf.update_ms = (float)update_ms;
-  inf.eval_launches = (int)round;
-  inf.eval_work = (double)done / (double)(d.S * d.ntiles);
-  if (info) *info = inf;
-  if (inf.n_nonfinite == c->P) return fail(c, GMCO_ENUMERIC, "every plan has a non-finite objective");
+  return summarize(c, round, ms, eval_ms, update_ms, done, info);
+}
+
+int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run_info* infos,
+                       int rounds_per_graph) {
+  if (!ctxs || n < 1 || !r || rounds_per_graph < 0) return GMCO_EINVAL;
+  gmco_ctx* c0 = ctxs[0];
+  if (!c0) return GMCO_EINVAL;
+  std::vector<int> dtypes(n);
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return GMCO_EINVAL;
+    if (ctxs[i]->device != c0->device) return fail(ctxs[i], GMCO_EINVAL, "contexts must share one device");
+    int rc = check_run(ctxs[i], r, &dtypes[i]);
+    if (rc) return rc;
+  }
+  GMCO_HIP(c0, hipSetDevice(c0->device));
+  // all work of the batch runs on a library-owned stream (graph capture needs
+  // a stream of its own), ordered after and before the caller's stream
+  if (!c0->gstream) {
+    GMCO_HIP(c0, hipStreamCreateWithFlags(&c0->gstream, hipStreamNonBlocking));
+    GMCO_HIP(c0, hipEventCreateWithFlags(&c0->gev, hipEventDisableTiming));
+  }
+  hipStream_t st = c0->gstream;
+  GMCO_HIP(c0, hipEventRecord(c0->gev, c0->stream));
+  GMCO_HIP(c0, hipStreamWaitEvent(st, c0->gev, 0));
+  const int R = rounds_per_graph > 0 ? (rounds_per_graph + 1) / 2 * 2 : 0;  // even: counter parity
+  std::vector<UpdateArgs> us(n);
+  std::vector<EvalArgs> as(n);
+  for (int i = 0; i < n; ++i) {
+    gmco_ctx* c = ctxs[i];
+    const Layout& L = c->lay;
+    GMCO_HIP(c, hipMemsetAsync(c->at<int>(L.active), 0, 2 * sizeof(int), st));
+    GMCO_HIP(c, hipMemsetAsync(c->at<unsigned long long>(L.work), 0, sizeof(unsigned long long), st));
+    GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), c->dim.Pp,
+                              c->dim.Kp, r->max_iter, r->resume_stopped, st));
+    us[i] = update_args(c, r);
+    as[i] = eval_args(c, c->at<float>(L.xt), true, dtypes[i]);
+    as[i].work = c->at<unsigned long long>(L.work);
+  }
+  const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
+  auto issue_round = [&](long long rd) -> int {
+    for (int i = 0; i < n; ++i) {
+      us[i].round = (int)rd;
+      GMCO_HIP(ctxs[i], launch_eval(as[i], dtypes[i], st));
+      GMCO_HIP(ctxs[i], launch_update(us[i], st));
+    }
+    return GMCO_OK;
+  };
+  auto all_done = [&](long long last_round) -> int {  // 1 done, 0 not, < 0 error
+    for (int i = 0; i < n; ++i)
+      GMCO_HIP(ctxs[i], hipMemcpyAsync(ctxs[i]->host_count, ctxs[i]->at<int>(ctxs[i]->lay.active) + (last_round & 1),
+                                       sizeof(int), hipMemcpyDeviceToHost, st));
+    GMCO_HIP(c0, hipStreamSynchronize(st));
+    long long tot = 0;
+    for (int i = 0; i < n; ++i) tot += *ctxs[i]->host_count;
+    return tot == 0 ? 1 : 0;
+  };
+  GMCO_HIP(c0, hipEventRecord(c0->ev0, st));
+  long long round = 0;
+  if (R == 0) {
+    const int check = r->check_every > 0 ? r->check_every : 16;
+    while (round < max_rounds) {
+      int rc = issue_round(round);
+      if (rc) return rc;
+      ++round;
+      if (round % check == 0) {
+        const int dn = all_done(round - 1);
+        if (dn < 0) return dn;
+        if (dn) break;
+      }
+    }
+  } else {
+    // capture R lockstep rounds of every case into one graph and replay it;
+    // rounds of plans that have stopped skip their work on the device
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GMCO_HIP(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = GMCO_OK;
+    for (int k = 0; k < R && rc == GMCO_OK; ++k) rc = issue_round(k);
+    hipError_t ee = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ee != hipSuccess) return hip_fail(c0, ee, "hipStreamEndCapture");
+    ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ee != hipSuccess) return hip_fail(c0, ee, "hipGraphInstantiate");
+    struct ExecGuard {
+      hipGraphExec_t e;
+      ~ExecGuard() { hipGraphExecDestroy(e); }
+    } eg{exec};
+    while (round < max_rounds) {
+      GMCO_HIP(c0, hipGraphLaunch(exec, st));
+      round += R;
+      const int dn = all_done(R - 1);
+      if (dn < 0) return dn;
+      if (dn) break;
+    }
+  }
+  GMCO_HIP(c0, hipEventRecord(c0->ev1, st));
+  GMCO_HIP(c0, hipEventSynchronize(c0->ev1));
+  GMCO_HIP(c0, hipEventRecord(c0->gev, st));
+  GMCO_HIP(c0, hipStreamWaitEvent(c0->stream, c0->gev, 0));
+  float ms = 0.f;
+  GMCO_HIP(c0, hipEventElapsedTime(&ms, c0->ev0, c0->ev1));
+  int status = GMCO_OK;
+  for (int i = 0; i < n; ++i) {
+    unsigned long long done = 0;
+    GMCO_HIP(ctxs[i], hipMemcpy(&done, ctxs[i]->at<void>(ctxs[i]->lay.work), sizeof(done), hipMemcpyDeviceToHost));
+    const int rc = summarize(ctxs[i], round, ms, 0.0, 0.0, done, infos ? &infos[i] : nullptr);
+    if (rc && !status) status = rc;
+  }
+  return status;
+}
+
+int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best_us) {
+  if (!c || reps < 1) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  if (dtype < 0) dtype = c->dtype;
+  if (!dtype_available(c->dtype, dtype)) return fail(c, GMCO_EINVAL, "dtype not available");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  Dims& d = c->dim;
+  std::vector<int> cand;
+  for (int s : {d.S, 4, 8, 12, 16, 20, 24, 28, 32})
+    if (s >= 1 && s <= d.S_cap && s <= d.nblocks && std::find(cand.begin(), cand.end(), s) == cand.end())
+      cand.push_back(s);
+  const int orig = d.S;
+  int best = orig;
+  float best_t = 1e30f;
+  for (int s : cand) {
+    d.S = s;
+    EvalArgs a = eval_args(c, c->at<float>(c->lay.xt), false, dtype);
+    GMCO_HIP(c, launch_eval(a, dtype, c->stream));  // warm-up
+    GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
+    for (int k = 0; k < reps; ++k) GMCO_HIP(c, launch_eval(a, dtype, c->stream));
+    GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
+    GMCO_HIP(c, hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    const float us = 1e3f * ms / reps;
+    if (us < best_t) {
+      best_t = us;
+      best = s;
+    }
+  }
+  d.S = best;
+  if (best_split) *best_split = best;
+  if (best_us) *best_us = best_t;
+  return GMCO_OK;
+}
+
+int gmco_set_split(gmco_ctx* c, int split) {
+  if (!c) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  if (split < 1 || split > c->dim.S_cap || split > c->dim.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
+  c->dim.S = split;
   return GMCO_OK;
 }
 

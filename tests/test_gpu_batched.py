@@ -1,0 +1,77 @@
+"""GPU checks of batched uneven cases: lockstep rounds over several contexts,
+plain or replayed from a captured HIP graph, give the same plans as running
+each case alone; the split autotuner keeps results within the parity bound."""
+import numpy as np
+import pytest
+
+import cases
+import oracle as O
+from gpu_common import PARAMS, announce, need_gpu, planner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _cases():
+    return [cases.make_case(6, 9, (400, 80, 150, 170), seed=41, jitter=0.2),
+            cases.make_case(11, 13, (1500, 300, 600, 611), seed=42, jitter=0.2),
+            cases.make_case(4, 7, (250, 50, 90, 95), seed=43, jitter=0.2)]
+
+
+def _planners(dtype="f32acc64"):
+    out = []
+    for i, c in enumerate(_cases()):
+        out.append(planner(c, cases.hidden_weights(40 + 30 * i, seed=60 + i), dtype=dtype))
+    return out
+
+
+def test_batched_rounds_match_single_case_runs():
+    from paper_1904_01567_amd import optimize_many
+    announce("batched vs single")
+    single = _planners()
+    for pl in single:
+        pl.optimize(max_iter=60)
+    ref = [pl.weights_x() for pl in single]
+    for R in (0, 6):
+        batch = _planners()
+        infos = optimize_many(batch, max_iter=60, rounds_per_graph=R)
+        for k, pl in enumerate(batch):
+            np.testing.assert_array_equal(pl.weights_x(), ref[k])
+            assert infos[k]["max_iters"] == 60
+        announce(f"rounds_per_graph={R}: identical to single-case runs")
+
+
+def test_graph_replays_match_eager_at_every_stage():
+    from paper_1904_01567_amd import optimize_many
+    announce("graph replays vs eager")
+    eager = _planners()
+    graph = _planners()
+    for cap in (10, 25, 40, 70):
+        optimize_many(eager, max_iter=cap, rounds_per_graph=0)
+        optimize_many(graph, max_iter=cap, rounds_per_graph=4)
+        for a, b in zip(eager, graph):
+            np.testing.assert_array_equal(a.weights_x(), b.weights_x())
+            np.testing.assert_array_equal(a.metrics()["F_run"], b.metrics()["F_run"])
+
+
+def test_autotuned_split_keeps_parity():
+    announce("autotune")
+    c, W = cases.case_c1(), cases.weights_c1()
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    pl = planner(c, W, dtype="f32acc64")
+    best, us = pl.autotune(reps=3)
+    announce(f"autotune: split {best}, {us:.1f} us per evaluation")
+    assert best >= 1 and us > 0
+    x = O.default_start(D, c.group, 15.0, W.shape[0]) * 1.1
+    F, g = pl.evaluate(x)
+    Fr, gr = O.objective_and_gradient_x(D, x, c.group, PARAMS, W)
+    assert np.max(np.abs(F - Fr) / Fr) <= 2e-5
+    assert np.abs(g - gr).max() <= 2e-4 * np.abs(gr).max()
+    for s in (1, 3):
+        pl.set_split(s)
+        F2, _ = pl.evaluate(x)
+        np.testing.assert_allclose(F2, Fr, rtol=2e-5)
