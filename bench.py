@@ -110,6 +110,56 @@ def cpu_baseline(n_plans: int, n_iters: int, iters_full: int):
                        f"{threads}), scaled to {iters_full} iterations per plan")
 
 
+def precision_report(args) -> int:
+    """Errors against the FP64 oracle's converged plans for each arithmetic,
+    at the benchmark's iteration cap (a BF16 or FP8 run stops earlier when
+    its line search stalls on rounding noise)."""
+    import numpy as np
+    import torch
+
+    import cases
+    from paper_1904_01567_amd import Planner, class_solution
+    golden = load_golden()
+    if golden is None:
+        print(json.dumps({"error": "no reference optima"}))
+        return 2
+    idx = np.array([q["index"] for q in golden["plans"]])
+    Fs = np.array([q["F"] for q in golden["plans"]])
+    V = np.array([q["V100_pct"][0] for q in golden["plans"]])
+    D10 = np.array([q["D10_pct"] for q in golden["plans"]])
+    case = cases.case_c2()
+    W = cases.weights_c2(args.plans)
+    iters = args.iters or 2000
+    configs = [("f32acc64", [("f32acc64", iters)]), ("f32", [("f32", iters)]),
+               ("bf16", [("bf16", iters)]), ("fp8", [("fp8", iters)]),
+               ("bf16", [("bf16", 150), ("f32acc64", iters)]),
+               ("fp8", [("fp8", 150), ("f32acc64", iters)])]
+    rows = []
+    for ctx_dtype, stages in configs:
+        pl = Planner(dtype=ctx_dtype, max_plans=args.plans)
+        pl.load(case, class_solution.VOLUME)
+        pl.set_weights(W)
+        ms = 0.0
+        for k, (dt, cap) in enumerate(stages):
+            ms += pl.optimize(max_iter=cap, dtype=dt, resume_stopped=k > 0)["device_ms"]
+        m = pl.metrics()
+        rel = (m["F64"][idx] - Fs) / Fs
+        dv = np.abs(m["V100_pct"][idx, 0] - V)
+        dd = np.abs(m["D10_pct"][idx] - D10)
+        rows.append({"stages": [f"{d}:{n}" for d, n in stages],
+                     "rel_F_excess_median": float(np.median(rel)), "rel_F_excess_max": float(rel.max()),
+                     "target_V100_abs_err_pp_max": float(dv.max()),
+                     "urethra_D10_abs_err_pp_max": float(dd[:, 1].max()),
+                     "bladder_D10_abs_err_pp_max": float(dd[:, 2].max()),
+                     "rectum_D10_abs_err_pp_max": float(dd[:, 3].max()),
+                     "within_tol": int(np.sum((rel <= TOL_F) & (dv <= TOL_V100))),
+                     "checked": int(idx.size), "device_ms": ms})
+        print(json.dumps(rows[-1]), flush=True)
+        pl.close()
+        torch.cuda.empty_cache()
+    return 0
+
+
 def batched(args) -> int:
     """Uneven-case batch: one context per case, lockstep rounds replayed from
     a captured graph; split counts autotuned once per (padded dwells, point
@@ -203,6 +253,9 @@ def main(argv=None) -> int:
                          "points, semi-axes +-20 %%) of --plans plans each in lockstep rounds "
                          "replayed from a captured HIP graph, splits autotuned per shape")
     ap.add_argument("--rounds-per-graph", type=int, default=16)
+    ap.add_argument("--precision-report", action="store_true",
+                    help="per arithmetic: objective, target V100 and OAR D10 errors of the "
+                         "sampled plans against the FP64 oracle optima")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB buffer once (reference for HBM byte counters)")
     args = ap.parse_args(argv)
@@ -233,6 +286,8 @@ def main(argv=None) -> int:
         return 0
     if args.batched:
         return batched(args)
+    if args.precision_report:
+        return precision_report(args)
     stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
     if args.ladder:
         stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]
