@@ -203,6 +203,30 @@ int gmco_evaluate(gmco_ctx* ctx, const double* x, double* F, double* g);
  * ENUMERIC (every plan non-finite at its start). */
 int gmco_optimize(gmco_ctx* ctx, const gmco_run* run, gmco_run_info* info);
 
+/* Plan evaluation and selection (Sec. 2.3.1, Sec. 2.4).  Validity after
+ * RTOG 0924: target V100 >= v100_min, urethra D10 < urethra_d10_max, bladder
+ * and rectum V75 below their limits; RTOG+ also needs V100 >= v100_plus. */
+typedef struct {
+  int target, urethra, bladder, rectum; /* structure indices */
+  double v100_min;        /* 90 % */
+  double v100_plus;       /* 95 % */
+  double urethra_d10_max; /* 118 % of the prescription (strict) */
+  double bladder_v75_max; /* 1 cc (strict) */
+  double rectum_v75_max;  /* 1 cc (strict) */
+} gmco_select_opts;
+
+/* Recompute the metrics of the current plans and select one: RTOG+ over
+ * RTOG over invalid; among valid plans the highest target V100; among
+ * invalid plans the lowest bladder + rectum V75 among those meeting the
+ * target and urethra criteria (all invalid plans if none does); ties to the
+ * lowest index.  Also each plan's class (2 RTOG+, 1 RTOG, 0 invalid) and
+ * whether no other plan is at least as good in every individual objective
+ * and strictly better in one (Sec. 2.2.4).  opts NULL = the values above for
+ * structures 0..3 = target, urethra, bladder, rectum.  plan_class and
+ * nondominated (P each) and nondominated_fraction may be NULL. */
+int gmco_select_plan(gmco_ctx* ctx, const gmco_select_opts* opts, int* best, int* plan_class,
+                     int* nondominated, double* nondominated_fraction);
+
 /* Batched uneven cases: run the same options on n contexts (one case and
  * weight batch each, one device) in lockstep rounds on the first context's
  * stream.  rounds_per_graph > 0 captures that many rounds (rounded up to even)

@@ -362,3 +362,57 @@ def plan_metrics(D, t, group, params, W, volume_cc, prescription_gy):
             m["D90_pct"][j] = d_percent(dj, 90, prescription_gy)
         out.append(m)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Plan evaluation and selection, Sec. 2.3.1 and Sec. 2.4.  RTOG 0924 validity:
+# target V100 >= 90 %, urethra D10 < 118 %, bladder V75 < 1 cc, rectum
+# V75 < 1 cc; RTOG+ asks target V100 >= 95 %.  Selection: RTOG+ over RTOG over
+# invalid; among valid plans the highest target V100; among invalid plans the
+# lowest bladder + rectum V75 among those meeting the target and urethra
+# criteria (reading: if none meets them, among all invalid plans); ties go to
+# the lowest plan index.
+# ---------------------------------------------------------------------------
+RTOG = dict(target=0, urethra=1, bladder=2, rectum=3, v100_min=90.0, v100_plus=95.0,
+            urethra_d10_max=118.0, bladder_v75_max=1.0, rectum_v75_max=1.0)
+
+
+def plan_class(m, c=RTOG):
+    """2 = RTOG+ valid, 1 = RTOG valid, 0 = invalid."""
+    v100 = m["V100_pct"][c["target"]]
+    ok_t = v100 >= c["v100_min"]
+    ok_u = m["D10_pct"][c["urethra"]] < c["urethra_d10_max"]
+    ok_b = m["V75_cc"][c["bladder"]] < c["bladder_v75_max"]
+    ok_r = m["V75_cc"][c["rectum"]] < c["rectum_v75_max"]
+    if not (ok_t and ok_u and ok_b and ok_r):
+        return 0
+    return 2 if v100 >= c["v100_plus"] else 1
+
+
+def select_plan(metrics, c=RTOG):
+    """Index of the selected plan."""
+    cls = [plan_class(m, c) for m in metrics]
+    best = max(cls)
+    idx = [p for p, k in enumerate(cls) if k == best]
+    if best > 0:
+        return max(idx, key=lambda p: (metrics[p]["V100_pct"][c["target"]], -p))
+    tu = [p for p in idx
+          if metrics[p]["V100_pct"][c["target"]] >= c["v100_min"]
+          and metrics[p]["D10_pct"][c["urethra"]] < c["urethra_d10_max"]]
+    pool = tu if tu else idx
+    return min(pool, key=lambda p: (metrics[p]["V75_cc"][c["bladder"]]
+                                    + metrics[p]["V75_cc"][c["rectum"]], p))
+
+
+def nondominated(f):
+    """(P,) bool: no other plan is at least as good in every individual
+    objective and strictly better in one (Sec. 2.2.4)."""
+    f = np.asarray(f, dtype=np.float64)
+    P = f.shape[0]
+    out = np.ones(P, dtype=bool)
+    for p in range(P):
+        for q in range(P):
+            if q != p and np.all(f[q] <= f[p]) and np.any(f[q] < f[p]):
+                out[p] = False
+                break
+    return out

@@ -28,7 +28,7 @@ EXPORTS = (
     "gmco_bind_workspace", "gmco_load_case", "gmco_set_weights", "gmco_evaluate",
     "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
     "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_optimize_many",
-    "gmco_autotune", "gmco_set_split", "gmco_last_error",
+    "gmco_autotune", "gmco_set_split", "gmco_select_plan", "gmco_last_error",
     "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
     "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
     "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
@@ -61,6 +61,12 @@ class gmco_run(C.Structure):
                 ("beta", C.c_double), ("max_ls", C.c_int), ("check_every", C.c_int),
                 ("time_kernels", C.c_int), ("resume_stopped", C.c_int), ("dtype", C.c_int),
                 ("reserved", C.c_int)]
+
+
+class gmco_select_opts(C.Structure):
+    _fields_ = [("target", C.c_int), ("urethra", C.c_int), ("bladder", C.c_int), ("rectum", C.c_int),
+                ("v100_min", C.c_double), ("v100_plus", C.c_double), ("urethra_d10_max", C.c_double),
+                ("bladder_v75_max", C.c_double), ("rectum_v75_max", C.c_double)]
 
 
 class gmco_run_info(C.Structure):
@@ -114,6 +120,8 @@ def load_library(path: Optional[str] = None):
                                        C.POINTER(gmco_run_info), C.c_int]
     lib.gmco_autotune.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_float)]
     lib.gmco_set_split.argtypes = [vp, C.c_int]
+    lib.gmco_select_plan.argtypes = [vp, C.POINTER(gmco_select_opts), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
     fp = C.POINTER(C.c_float)
     lib.gmco_mlp_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int]
     lib.gmco_mlp_destroy.argtypes = [vp]
@@ -308,6 +316,17 @@ class Planner:
 
     def set_split(self, split: int):
         self._check(self.lib.gmco_set_split(self._ctx, int(split)), "set_split")
+
+    def select_plan(self):
+        """(selected index, per-plan RTOG class, non-dominated flags, fraction)."""
+        best = C.c_int()
+        cls = np.empty(self.P, dtype=np.int32)
+        nd = np.empty(self.P, dtype=np.int32)
+        frac = C.c_double()
+        ip = C.POINTER(C.c_int)
+        self._check(self.lib.gmco_select_plan(self._ctx, None, C.byref(best), cls.ctypes.data_as(ip),
+                                              nd.ctypes.data_as(ip), C.byref(frac)), "select_plan")
+        return int(best.value), cls, nd.astype(bool), float(frac.value)
 
     def case_features(self) -> np.ndarray:
         out = np.empty(self.G * 16, dtype=np.float32)

@@ -23,7 +23,7 @@ struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t Wst, t0st, xst, Fst, gst;
   size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work;
-  size_t t64, d64, metrics, hist, feat;
+  size_t t64, d64, metrics, hist, feat, sel;
   size_t total;
 };
 
@@ -162,6 +162,7 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.d64 = take((size_t)std::max(d.Pp, dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp * 8);
   L.metrics = take((size_t)d.Pp * sizeof(gmco_plan_metrics));
   L.hist = take(kGmax * 16 * 4);
+  L.sel = take((size_t)d.Pp * 3 * 4 + 16);
   L.feat = take(kGmax * 16 * 4);
   (void)G;
   L.total = off;
@@ -769,6 +770,46 @@ int gmco_get_weights_x(gmco_ctx* c, double* x) {
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
   for (int p = 0; p < c->P; ++p)
     for (int l = 0; l < K; ++l) x[(size_t)p * K + l] = xs[(size_t)p * Kp + l];
+  return GMCO_OK;
+}
+
+namespace {
+int compute_metrics(gmco_ctx* c) {
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  GMCO_HIP(c, launch_export_t(c->at<float>(L.x), d.Pp, d.K, d.Kp, c->at<double>(L.t64), d.Kp, c->stream));
+  GMCO_HIP(c, launch_dose64(c->at<double>(L.D64), c->at<double>(L.t64), d.Mp, d.Kp, d.Pp, c->at<double>(L.d64), c->stream));
+  GMCO_HIP(c, launch_metrics(c->at<double>(L.d64), c->at<double>(L.W64), c->at<PlanState>(L.ps), c->P, d.Mp,
+                             c->at<int>(L.goff), c->at<int>(L.gcnt), c->G, c->at<double>(L.gparams),
+                             c->at<double>(L.volume), c->rx, c->at<gmco_plan_metrics>(L.metrics), c->stream));
+  return GMCO_OK;
+}
+}  // namespace
+
+int gmco_select_plan(gmco_ctx* c, const gmco_select_opts* opts, int* best, int* plan_class, int* nondominated,
+                     double* nondominated_fraction) {
+  if (!c) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  gmco_select_opts o{0, 1, 2, 3, 90.0, 95.0, 118.0, 1.0, 1.0};
+  if (opts) o = *opts;
+  for (int j : {o.target, o.urethra, o.bladder, o.rectum})
+    if (j < 0 || j >= c->G) return fail(c, GMCO_EINVAL, "structure index out of range");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  int rc = compute_metrics(c);
+  if (rc) return rc;
+  const int P = c->P, Pp = c->dim.Pp;
+  int* cls = c->at<int>(c->lay.sel);
+  int* tu = cls + Pp;
+  int* nd = tu + Pp;
+  int* res = nd + Pp;
+  GMCO_HIP(c, launch_select(c->at<gmco_plan_metrics>(c->lay.metrics), P, c->G, o, cls, tu, nd, res, c->stream));
+  int h[2] = {0, 0};
+  GMCO_HIP(c, hipMemcpyAsync(h, res, 8, hipMemcpyDeviceToHost, c->stream));
+  if (plan_class) GMCO_HIP(c, hipMemcpyAsync(plan_class, cls, (size_t)P * 4, hipMemcpyDeviceToHost, c->stream));
+  if (nondominated) GMCO_HIP(c, hipMemcpyAsync(nondominated, nd, (size_t)P * 4, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  if (best) *best = h[0];
+  if (nondominated_fraction) *nondominated_fraction = (double)h[1] / (double)P;
   return GMCO_OK;
 }
 

@@ -118,6 +118,8 @@ hipError_t launch_metrics(const double* d64, const double* W64, const PlanState*
                           const double* volume_cc, double prescription, gmco_plan_metrics* out,
                           hipStream_t st);
 
+hipError_t launch_select(const gmco_plan_metrics* m, int P, int G, const gmco_select_opts& o, int* cls,
+                         int* meets_tu, int* nd, int* out, hipStream_t st);
 hipError_t launch_features(const double* dwell, const double* pts, const int* perm, const int* goff,
                            const int* gcnt, int K, int G, unsigned* hist, float* out, hipStream_t st);
 

@@ -189,7 +189,127 @@ __global__ void k_metrics_final(const double* __restrict__ W64, const PlanState*
   m->reserved = 0;
 }
 
+// RTOG 0924 classes (Sec. 2.3.1): 2 = RTOG+ valid, 1 = RTOG valid, 0 = invalid.
+__global__ void k_classify(const gmco_plan_metrics* __restrict__ m, int P, gmco_select_opts o,
+                           int* __restrict__ cls, int* __restrict__ meets_tu) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const double v100 = m[p].V100_pct[o.target];
+  const bool ok_t = v100 >= o.v100_min;
+  const bool ok_u = m[p].D10_pct[o.urethra] < o.urethra_d10_max;
+  const bool ok_b = m[p].V75_cc[o.bladder] < o.bladder_v75_max;
+  const bool ok_r = m[p].V75_cc[o.rectum] < o.rectum_v75_max;
+  cls[p] = (ok_t && ok_u && ok_b && ok_r) ? (v100 >= o.v100_plus ? 2 : 1) : 0;
+  meets_tu[p] = (ok_t && ok_u) ? 1 : 0;
+}
+
+// Plan p is dominated when another plan is at least as good in every
+// individual objective and strictly better in one (Sec. 2.2.4).
+__global__ void k_pareto(const gmco_plan_metrics* __restrict__ m, int P, int G, int* __restrict__ nd) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int dominated = 0;
+  for (int q = 0; q < P && !dominated; ++q) {
+    if (q == p) continue;
+    bool all_le = true, any_lt = false;
+    for (int j = 0; j < G; ++j) {
+      const double a = m[q].f_organ[j], b = m[p].f_organ[j];
+      all_le = all_le && (a <= b);
+      any_lt = any_lt || (a < b);
+    }
+    dominated = (all_le && any_lt) ? 1 : 0;
+  }
+  nd[p] = dominated ? 0 : 1;
+}
+
+// Selection (Sec. 2.4): RTOG+ over RTOG over invalid; among valid plans the
+// highest target V100; among invalid plans the lowest bladder + rectum V75
+// among those meeting the target and urethra criteria (all invalid plans if
+// none does); ties to the lowest index.  One workgroup.
+__global__ __launch_bounds__(1024) void k_select(const gmco_plan_metrics* __restrict__ m,
+                                                 const int* __restrict__ cls,
+                                                 const int* __restrict__ meets_tu, const int* __restrict__ nd,
+                                                 int P, gmco_select_opts o, int* __restrict__ out) {
+  __shared__ int s_i[1024];
+  __shared__ double s_k[1024];
+  const int t = threadIdx.x;
+  // best class and whether an invalid plan meets target and urethra
+  int bc = 0, tu = 0, nnd = 0;
+  for (int p = t; p < P; p += blockDim.x) {
+    bc = max(bc, cls[p]);
+    tu |= (cls[p] == 0 && meets_tu[p]) ? 1 : 0;
+    nnd += nd[p];
+  }
+  s_i[t] = bc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) s_i[t] = max(s_i[t], s_i[t + w]);
+    __syncthreads();
+  }
+  const int best_class = s_i[0];
+  __syncthreads();
+  s_i[t] = tu;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) s_i[t] = s_i[t] | s_i[t + w];
+    __syncthreads();
+  }
+  const int any_tu = s_i[0];
+  __syncthreads();
+  s_i[t] = nnd;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) s_i[t] += s_i[t + w];
+    __syncthreads();
+  }
+  const int n_nd = s_i[0];
+  __syncthreads();
+  // smallest key wins, ties to the lowest index
+  int bi = -1;
+  double bk = 0.0;
+  for (int p = t; p < P; p += blockDim.x) {
+    if (cls[p] != best_class) continue;
+    if (best_class == 0 && any_tu && !meets_tu[p]) continue;
+    const double key = best_class > 0 ? -m[p].V100_pct[o.target]
+                                       : m[p].V75_cc[o.bladder] + m[p].V75_cc[o.rectum];
+    if (bi < 0 || key < bk) {
+      bi = p;
+      bk = key;
+    }
+  }
+  s_i[t] = bi;
+  s_k[t] = bk;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      const int i2 = s_i[t + w];
+      const double k2 = s_k[t + w];
+      if (i2 >= 0 && (s_i[t] < 0 || k2 < s_k[t] || (k2 == s_k[t] && i2 < s_i[t]))) {
+        s_i[t] = i2;
+        s_k[t] = k2;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = s_i[0];
+    out[1] = n_nd;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_select(const gmco_plan_metrics* m, int P, int G, const gmco_select_opts& o, int* cls,
+                         int* meets_tu, int* nd, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_classify, dim3((P + 255) / 256), dim3(256), 0, st, m, P, o, cls, meets_tu);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pareto, dim3((P + 255) / 256), dim3(256), 0, st, m, P, G, nd);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st, m, cls, meets_tu, nd, P, o, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,
                            hipStream_t st) {

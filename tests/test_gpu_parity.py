@@ -327,3 +327,31 @@ def test_resume_continues_to_the_same_point():
     np.testing.assert_array_equal(ma["iterations"], mb["iterations"])
     # the resumed run re-evaluates its start point: identical arithmetic
     np.testing.assert_allclose(mb["F_run"], ma["F_run"], rtol=1e-5)
+
+
+def test_plan_selection_matches_oracle():
+    # RTOG classes, selection and non-dominance on the device against the
+    # oracle's, at seeded dwell times (x stored in FP32 as on the device).
+    announce("plan selection")
+    c, D = oracle_dose_rate("case_c1")
+    # oracle-optimised plans of 8 weight vectors, perturbed by seeded noise, so
+    # that RTOG+, RTOG and invalid plans all occur
+    W8 = cases.weights_c1()
+    x0 = O.default_start(D, c.group, 15.0, 8)
+    r = O.optimize(D, c.group, PARAMS, W8, x0, O.LbfgsOptions(max_iter=300))
+    W = np.repeat(W8, 12, axis=0)
+    u = cases.uniform_draws((96, c.K), seed=32)
+    scale = np.repeat(np.linspace(0.9, 1.12, 12)[None, :], 8, axis=0).reshape(-1, 1)
+    t0 = np.repeat(r["t"], 12, axis=0) * scale * (0.97 + 0.06 * u) + 1e-6
+    pl = planner(c, W, t0=t0)
+    best, cls, nd, frac = pl.select_plan()
+    x32 = np.sqrt(t0).astype(np.float32).astype(np.float64)
+    mref = O.plan_metrics(D, x32 * x32, c.group, PARAMS, W, c.volume_cc, 15.0)
+    cref = np.array([O.plan_class(m) for m in mref])
+    ndref = O.nondominated(np.stack([m["f_organ"] for m in mref]))
+    announce(f"selection: best {best}, classes {np.bincount(cls, minlength=3)}, nd {frac:.3f}")
+    np.testing.assert_array_equal(cls, cref)
+    np.testing.assert_array_equal(nd, ndref)
+    assert best == O.select_plan(mref)
+    assert frac == pytest.approx(ndref.mean())
+    assert len(set(cref.tolist())) >= 2

@@ -445,3 +445,29 @@ def test_library_class_solution_matches_golden():
     for i, o in enumerate(cs.STRUCTURES):
         np.testing.assert_array_equal(cs.SURFACE[i], rows[(o, "surface")])
         np.testing.assert_array_equal(cs.VOLUME[i], rows[(o, "volume")])
+
+
+def _m(v100, d10u, v75b, v75r):
+    return {"V100_pct": np.array([v100, 0, 0, 0.0]), "D10_pct": np.array([0, d10u, 0, 0.0]),
+            "V75_cc": np.array([0, 0, v75b, v75r])}
+
+
+def test_rtog_classes_and_selection_by_hand():
+    ms = [_m(93.0, 110.0, 0.5, 0.5),    # RTOG
+          _m(96.0, 117.9, 0.9, 0.1),    # RTOG+
+          _m(97.0, 118.0, 0.1, 0.1),    # urethra fails (D10 < 118 is strict)
+          _m(95.0, 100.0, 0.2, 0.2),    # RTOG+ (V100 >= 95 inclusive)
+          _m(89.9, 100.0, 0.0, 0.0)]    # target fails
+    assert [O.plan_class(m) for m in ms] == [1, 2, 0, 2, 0]
+    assert O.select_plan(ms) == 1                       # highest V100 among RTOG+
+    assert O.select_plan([ms[0], _m(93.0, 1.0, 0, 0)]) == 0   # tie -> lowest index
+    inv = [_m(91.0, 120.0, 0.1, 0.1), _m(92.0, 100.0, 1.5, 0.4), _m(92.0, 100.0, 1.2, 0.2),
+           _m(80.0, 100.0, 0.0, 0.0)]
+    # invalid only: lowest bladder + rectum V75 among plans meeting target and urethra
+    assert O.select_plan(inv) == 2
+    assert O.select_plan([inv[0], inv[3]]) == 1         # none meets both: all invalid
+
+
+def test_nondominated_by_hand():
+    f = np.array([[1.0, 2.0], [2.0, 1.0], [2.0, 2.0], [1.0, 2.0], [0.5, 3.0]])
+    np.testing.assert_array_equal(O.nondominated(f), [True, True, False, True, True])
