@@ -110,6 +110,73 @@ def cpu_baseline(n_plans: int, n_iters: int, iters_full: int):
                        f"{threads}), scaled to {iters_full} iterations per plan")
 
 
+def eps_sweep(args) -> int:
+    """Stop rule trade-off (Sec. 2.2.4 and Fig. 3a of the paper): relative
+    objective variation eps against time and the non-dominated fraction."""
+    import numpy as np
+    import torch
+
+    import cases
+    from paper_1904_01567_amd import Planner, class_solution
+    case = cases.case_c2()
+    W = cases.weights_c2(args.plans)
+    golden = load_golden()
+    pl = Planner(dtype=args.dtype, max_plans=args.plans)
+    pl.load(case, class_solution.VOLUME)
+    rows = []
+    for eps in [float(v) for v in args.eps_sweep.split(",")]:
+        pl.set_weights(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pl.optimize(max_iter=args.iters or 20000, eps=eps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best, cls, nd, frac = pl.select_plan()
+        # kernel split of the same run, timed separately (events add overhead)
+        pl.set_weights(W)
+        tk = pl.optimize(max_iter=args.iters or 20000, eps=eps, time_kernels=True)
+        m = pl.metrics()
+        rep = tolerance_report(m, golden)
+        rows.append({"eps": eps, "seconds": dt, "rounds": info["rounds"],
+                     "max_iters": info["max_iters"], "median_iters": float(np.median(m["iterations"])),
+                     "nondominated_fraction": frac, "rtog_plus": int(np.sum(cls == 2)),
+                     "rtog": int(np.sum(cls == 1)), "selected": best,
+                     "eval_full_equivalents": tk["eval_work"], "eval_ms": tk["eval_ms"],
+                     "update_ms": tk["update_ms"], "tol": rep})
+        rows[-1]["speedup_vs_first"] = rows[0]["seconds"] / dt
+        print(json.dumps(rows[-1]), flush=True)
+    return 0
+
+
+def plan_sweep(args) -> int:
+    """Time and device memory against the number of plans (Fig. 4 of the
+    paper): one context per batch size, same case, same iteration cap."""
+    import torch
+
+    import cases
+    from paper_1904_01567_amd import Planner, class_solution
+    case = cases.case_c2()
+    iters = args.iters or ITERS.get(args.dtype, 2000)
+    for P in [int(v) for v in args.plan_sweep.split(",")]:
+        W = cases.weights_c2(P)
+        pl = Planner(dtype=args.dtype, max_plans=P)
+        pl.load(case, class_solution.VOLUME)
+        ws = pl.workspace_bytes(case.M, case.K)
+        pl.set_weights(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pl.optimize(max_iter=iters)
+        pl.metrics()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"plans": P, "seconds": dt, "ms_per_plan": 1e3 * dt / P,
+                          "plans_per_s": P / dt, "rounds": info["rounds"],
+                          "workspace_GB": ws / 1e9, "iterations": iters}), flush=True)
+        pl.close()
+        torch.cuda.empty_cache()
+    return 0
+
+
 def precision_report(args) -> int:
     """Errors against the FP64 oracle's converged plans for each arithmetic,
     at the benchmark's iteration cap (a BF16 or FP8 run stops earlier when
@@ -253,6 +320,11 @@ def main(argv=None) -> int:
                          "points, semi-axes +-20 %%) of --plans plans each in lockstep rounds "
                          "replayed from a captured HIP graph, splits autotuned per shape")
     ap.add_argument("--rounds-per-graph", type=int, default=16)
+    ap.add_argument("--eps-sweep", type=str, default=None,
+                    help="comma-separated stop thresholds: time, iterations and non-dominated "
+                         "fraction at each (speed-up relative to the first)")
+    ap.add_argument("--plan-sweep", type=str, default=None,
+                    help="comma-separated batch sizes: time and device memory at each")
     ap.add_argument("--precision-report", action="store_true",
                     help="per arithmetic: objective, target V100 and OAR D10 errors of the "
                          "sampled plans against the FP64 oracle optima")
@@ -288,6 +360,10 @@ def main(argv=None) -> int:
         return batched(args)
     if args.precision_report:
         return precision_report(args)
+    if args.eps_sweep:
+        return eps_sweep(args)
+    if args.plan_sweep:
+        return plan_sweep(args)
     stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
     if args.ladder:
         stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]

@@ -132,8 +132,9 @@ typedef struct {
   float eval_ms;       /* sum of evaluation-kernel durations (time_kernels = 1) */
   float update_ms;     /* sum of L-BFGS update-kernel durations (time_kernels = 1) */
   int eval_launches;   /* evaluation launches */
-  double eval_work;    /* evaluation work done, in full-batch launch equivalents
-                          (tiles whose plans had all stopped are skipped) */
+  double eval_work;    /* plan evaluations done / batch size: full-batch launch
+                          equivalents (stopped plans are compacted out of every
+                          evaluation) */
 } gmco_run_info;
 
 typedef struct {
@@ -233,17 +234,21 @@ int gmco_select_plan(gmco_ctx* ctx, const gmco_select_opts* opts, int* best, int
  * of every case into one HIP graph and replays it until every plan of every
  * case has stopped; 0 issues plain launches.  infos has n entries (NULL
  * allowed); device_ms is the whole batch's time.  Plans that stop early keep
- * skipping their share on the device.  Errors as gmco_optimize. */
+ * compacted out of every later round on the device.  Errors as gmco_optimize. */
 int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_run_info* infos,
                        int rounds_per_graph);
 
 /* Autotuner: time the evaluation kernel of this case and batch for each
  * candidate split count of the point range (workgroups per plan tile; up to
  * 32) and keep the fastest.  reps timed launches per candidate on the
- * context stream.  Needs a weight batch.  best_split / best_us may be NULL. */
+ * context stream.  Needs a weight batch.  best_split / best_us may be NULL.
+ * The tuned split is used by rounds in which every plan tile of the batch
+ * capacity is active; rounds with fewer active plans (stopped plans are
+ * compacted out) choose their split on the device to fill the compute units. */
 int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* best_us);
 
-/* Set the split count directly (e.g. from a cache of autotuned shapes). */
+/* Set the split count directly (e.g. from a cache of autotuned shapes); same
+ * scope as the autotuner's.  1 <= split <= the autotuner's range. */
 int gmco_set_split(gmco_ctx* ctx, int split);
 
 /* t = x^2 of every plan, P x K, FP64 (computed on the device). */

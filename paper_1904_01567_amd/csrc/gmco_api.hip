@@ -22,14 +22,17 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t Wst, t0st, xst, Fst, gst;
-  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work;
+  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, act, slot, rt;
   size_t t64, d64, metrics, hist, feat, sel;
   size_t total;
 };
 
 struct Dims {
   int M = 0, K = 0, Mp = 0, Kp = 0, Pp = 0, S = 1, ntiles = 1, nblocks = 0;
-  int S_cap = 1;  // split counts up to this fit the partial buffers (autotuning range)
+  int S_cap = 1;      // split counts up to this fit the partial buffers (autotuning range)
+  int S_tuned = 0;    // split set by the caller or the autotuner, 0 = heuristic
+  int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
+  int grid_cap = 1;   // workgroups (of kPT columns) the partial buffers hold
 };
 
 constexpr int kSplitTuneMax = 32;
@@ -106,10 +109,17 @@ Dims make_dims(int M, int K, int Pmax, int n_cu) {
   d.nblocks = d.Mp / kBM;
   d.Pp = round_up(Pmax, kPT);
   d.ntiles = d.Pp / kPT;
-  int S = std::max(1, n_cu / d.ntiles);
-  if (S >= 8) S -= S % 8;
-  d.S = std::max(1, std::min(S, d.nblocks));
+  d.S = choose_split(d.ntiles, d.nblocks, n_cu, kSplitMax);
   d.S_cap = std::max(d.S, std::min(kSplitTuneMax, d.nblocks));
+  // compacted rounds choose their split on the device for 1..ntiles active
+  // tiles, with the 16-point (FP32) or 32-point (BF16, FP8) block count
+  d.grid_heur = 1;
+  for (int nt = 1; nt <= d.ntiles; ++nt) {
+    const int s16 = choose_split(nt, d.nblocks, n_cu, kSplitMax);
+    const int s32 = choose_split(nt, d.Mp / 32, n_cu, kSplitMax);
+    d.grid_heur = std::max(d.grid_heur, nt * std::max(s16, s32));
+  }
+  d.grid_cap = std::max(d.grid_heur, d.ntiles * d.S_cap);
   return d;
 }
 
@@ -153,8 +163,12 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.Yh = take(PK * m * 4);
   L.rho = take((size_t)d.Pp * m * 8);
   L.ps = take((size_t)d.Pp * sizeof(PlanState));
-  L.Gpart = take((size_t)d.S_cap * PK * 4);
-  L.Fpart = take((size_t)d.S_cap * d.Pp * 8);
+  L.Gpart = take((size_t)d.grid_cap * kPT * d.Kp * 4);
+  L.Fpart = take((size_t)d.grid_cap * kPT * 8);
+  L.Gsum = take(PK * 4);
+  L.act = take((size_t)d.Pp * 4);
+  L.slot = take((size_t)d.Pp * 4);
+  L.rt = take(sizeof(RoundTable));
   L.active = take(2 * sizeof(int));
   L.work = take(sizeof(unsigned long long));
   L.t64 = take(PK * 8);
@@ -181,7 +195,14 @@ int copy_h2d(gmco_ctx* c, void* dst, const void* src, size_t bytes) {
   return GMCO_OK;
 }
 
-EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped, int dtype) {
+// Point blocks over which a compacted round splits, for the kernel of dtype.
+int split_blocks(const gmco_ctx* c, int dtype) {
+  return is_low_precision(dtype) ? c->dim.Mp / 32 : c->dim.nblocks;
+}
+
+// compacted: the active-plan list and round table written by k_compact
+// decide the columns and the split; otherwise every plan, host split.
+EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype) {
   EvalArgs a{};
   a.D = is_low_precision(dtype) ? c->at<void>(c->lay.Dlp) : c->at<void>(c->lay.D32);
   a.DT = c->at<void>(c->lay.DTlp);
@@ -189,7 +210,8 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped, int dty
   a.grp = c->at<int>(c->lay.grp);
   a.x = x;
   a.wn = c->at<float>(c->lay.wn);
-  a.ps = skip_stopped ? c->at<PlanState>(c->lay.ps) : nullptr;
+  a.act = compacted ? c->at<int>(c->lay.act) : nullptr;
+  a.rt = compacted ? c->at<RoundTable>(c->lay.rt) : nullptr;
   a.Gpart = c->at<float>(c->lay.Gpart);
   a.Fpart = c->at<double>(c->lay.Fpart);
   a.Mp = c->dim.Mp;
@@ -198,15 +220,23 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool skip_stopped, int dty
   a.nblocks = c->dim.nblocks;
   a.S = c->dim.S;
   a.ntiles = c->dim.ntiles;
+  a.grid = compacted ? std::max(c->dim.grid_heur, c->dim.ntiles * c->dim.S_tuned) : a.S * a.ntiles;
   a.gt = c->gt;
   return a;
+}
+
+hipError_t launch_compact_ctx(const gmco_ctx* c, int dtype, hipStream_t st) {
+  const Layout& L = c->lay;
+  return launch_compact(c->at<PlanState>(L.ps), c->P, split_blocks(c, dtype), c->n_cu, c->dim.S_tuned,
+                        c->dim.ntiles, c->at<int>(L.act), c->at<int>(L.slot), c->at<RoundTable>(L.rt),
+                        c->at<unsigned long long>(L.work), st);
 }
 
 UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
   const Layout& L = c->lay;
   const Dims& d = c->dim;
   UpdateArgs u{};
-  u.Gpart = c->at<float>(L.Gpart);
+  u.Gsum = c->at<float>(L.Gsum);
   u.Fpart = c->at<double>(L.Fpart);
   u.x = c->at<float>(L.x);
   u.g = c->at<float>(L.g);
@@ -217,9 +247,10 @@ UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
   u.rho = c->at<double>(L.rho);
   u.ps = c->at<PlanState>(L.ps);
   u.active_count = c->at<int>(L.active);
+  u.slot = c->at<int>(L.slot);
+  u.rt = c->at<RoundTable>(L.rt);
   u.Kp = d.Kp;
   u.Pp = d.Pp;
-  u.S = d.S;
   u.m = c->m;
   u.K = d.K;
   u.max_iter = r->max_iter;
@@ -258,7 +289,7 @@ int summarize(gmco_ctx* c, long long rounds, float ms, double eval_ms, double up
   inf.eval_ms = (float)eval_ms;
   inf.update_ms = (float)update_ms;
   inf.eval_launches = (int)rounds;
-  inf.eval_work = (double)work / (double)(c->dim.S * c->dim.ntiles);
+  inf.eval_work = (double)work / (double)c->P;  // plan evaluations / batch size
   if (info) *info = inf;
   if (inf.n_nonfinite == c->P) return fail(c, GMCO_ENUMERIC, "every plan has a non-finite objective");
   return GMCO_OK;
@@ -521,7 +552,6 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
                             r->max_iter, r->resume_stopped, c->stream));
   UpdateArgs u = update_args(c, r);
   EvalArgs a = eval_args(c, c->at<float>(L.xt), true, dtype);
-  a.work = work;
   const int check = r->check_every > 0 ? r->check_every : 16;
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
   // optional per-launch timing: 4 events per round of one check block
@@ -561,12 +591,14 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   int in_block = 0;
   for (; round < max_rounds; ++round) {
     u.round = (int)round;
+    GMCO_HIP(c, launch_compact_ctx(c, dtype, c->stream));
     if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
     GMCO_HIP(c, launch_eval(a, dtype, c->stream));
     if (r->time_kernels) {
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 1], c->stream));
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 2], c->stream));
     }
+    GMCO_HIP(c, launch_reduce_g(a.Gpart, a.rt, d.Pp, d.Kp, c->at<float>(L.Gsum), c->stream));
     GMCO_HIP(c, launch_update(u, c->stream));
     if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 3], c->stream));
     ++in_block;
@@ -625,13 +657,14 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
                               c->dim.Kp, r->max_iter, r->resume_stopped, st));
     us[i] = update_args(c, r);
     as[i] = eval_args(c, c->at<float>(L.xt), true, dtypes[i]);
-    as[i].work = c->at<unsigned long long>(L.work);
   }
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
   auto issue_round = [&](long long rd) -> int {
     for (int i = 0; i < n; ++i) {
       us[i].round = (int)rd;
+      GMCO_HIP(ctxs[i], launch_compact_ctx(ctxs[i], dtypes[i], st));
       GMCO_HIP(ctxs[i], launch_eval(as[i], dtypes[i], st));
+      GMCO_HIP(ctxs[i], launch_reduce_g(as[i].Gpart, as[i].rt, ctxs[i]->dim.Pp, ctxs[i]->dim.Kp, ctxs[i]->at<float>(ctxs[i]->lay.Gsum), st));
       GMCO_HIP(ctxs[i], launch_update(us[i], st));
     }
     return GMCO_OK;
@@ -661,7 +694,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     }
   } else {
     // capture R lockstep rounds of every case into one graph and replay it;
-    // rounds of plans that have stopped skip their work on the device
+    // each round's compaction drops the plans that have stopped
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     GMCO_HIP(c0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -735,6 +768,7 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
     }
   }
   d.S = best;
+  d.S_tuned = best;
   if (best_split) *best_split = best;
   if (best_us) *best_us = best_t;
   return GMCO_OK;
@@ -745,6 +779,7 @@ int gmco_set_split(gmco_ctx* c, int split) {
   if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
   if (split < 1 || split > c->dim.S_cap || split > c->dim.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
   c->dim.S = split;
+  c->dim.S_tuned = split;
   return GMCO_OK;
 }
 

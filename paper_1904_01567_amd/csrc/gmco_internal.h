@@ -14,6 +14,7 @@ constexpr int kBM = 16;   // dose points per inner block of the evaluation kerne
 constexpr int kPT = 64;   // plans per workgroup tile of the evaluation kernel
 constexpr int kKAlign = 32;
 constexpr int kMAlign = 32;  // points: a multiple of every kernel's block
+constexpr int kSplitMax = 256;  // largest split-M count the heuristic picks
 
 // Internal plan states; 0..5 match gmco_plan_status.
 enum : int {
@@ -51,6 +52,37 @@ struct GroupTable {
   double prm64[kGmax + 1][4];
 };
 
+// Per-round shape of the compacted evaluation, written on the device before
+// each evaluation: the active plans occupy compact columns 0..nact-1, which
+// form ntiles tiles of kPT; every tile is split S ways over the points.
+struct RoundTable {
+  int nact;
+  int ntiles;
+  int S;
+  int pad;
+};
+
+// Split count for ntiles plan tiles over nblocks point blocks on n_cu compute
+// units (one workgroup per CU at a time): minimises the number of workgroup
+// waves times the blocks per workgroup (plus a pipeline fill of two blocks),
+// with a slight preference for multiples of 8 (the XCD-aware tile mapping).
+__host__ __device__ inline int choose_split(int ntiles, int nblocks, int n_cu, int s_max) {
+  if (ntiles <= 0 || nblocks <= 0) return 1;
+  const int hi = s_max < nblocks ? s_max : nblocks;
+  int best = 1;
+  double best_c = 0.0;
+  for (int S = 1; S <= hi; ++S) {
+    const double waves = (double)((ntiles * S + n_cu - 1) / n_cu);
+    const double per = (double)((nblocks + S - 1) / S + 2);
+    const double c = waves * per * ((S & 7) ? 1.02 : 1.0);
+    if (S == 1 || c < best_c) {
+      best_c = c;
+      best = S;
+    }
+  }
+  return best;
+}
+
 struct EvalArgs {
   const void* D;          // [Mp][Kp] dose-rate matrix in the run dtype
   const void* DT;         // [Kp][Mp] transposed copy (BF16 / FP8 only)
@@ -58,19 +90,24 @@ struct EvalArgs {
   const int* grp;         // [Mp] structure index, kGmax for padding
   const float* x;         // [Pp][Kp] points to evaluate (dwell weights)
   const float* wn;        // [Pp][kGmax] w_j / N_j
-  const PlanState* ps;    // plan states; NULL evaluates every tile
-  float* Gpart;           // [S][Pp][Kp] split-M partial back-projections
-  double* Fpart;          // [S][Pp] split-M partial objectives
-  unsigned long long* work;  // optional count of workgroups that did not skip
+  // Compacted rounds: act[j] is the plan in compact column j and rt holds
+  // the round's shape; the partials are then [S][rt.ntiles * kPT][Kp] by
+  // compact column.  Both NULL: every plan, column = plan, host S and
+  // ntiles, partials [S][Pp][Kp].
+  const int* act;
+  const RoundTable* rt;
+  float* Gpart;           // split-M partial back-projections
+  double* Fpart;          // split-M partial objectives
   int Mp, Kp, Pp;
   int nblocks;            // Mp / kBM (16-point blocks)
-  int S;                  // M splits
-  int ntiles;             // Pp / kPT
+  int S;                  // M splits (uncompacted form)
+  int ntiles;             // Pp / kPT (uncompacted form)
+  int grid;               // workgroups launched; those past S * ntiles exit
   GroupTable gt;
 };
 
 struct UpdateArgs {
-  const float* Gpart;
+  const float* Gsum;      // [Pp][Kp] summed gradient partials by compact column
   const double* Fpart;
   float* x;       // [Pp][Kp] current iterate
   float* g;       // [Pp][Kp] gradient at x
@@ -81,7 +118,9 @@ struct UpdateArgs {
   double* rho;    // [Pp][m]
   PlanState* ps;
   int* active_count;  // [2]
-  int Kp, Pp, S, m, K;
+  const int* slot;    // [Pp] compact column of each active plan
+  const RoundTable* rt;
+  int Kp, Pp, m, K;
   int max_iter, max_ls;
   double eps, c1, beta;
   int round;
@@ -105,6 +144,11 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t st);
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
                               int P, int Pp, int K, int Kp, double* F, double* g,
                               hipStream_t st);
+hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
+                           hipStream_t st);
+hipError_t launch_compact(const PlanState* ps, int P, int nblocks, int n_cu, int s_tuned,
+                          int ntiles_full, int* act, int* slot, RoundTable* rt,
+                          unsigned long long* work, hipStream_t st);
 hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int Pp, int Kp, int max_iter,
                          int resume_stopped, hipStream_t st);
 hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,

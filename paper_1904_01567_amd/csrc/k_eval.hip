@@ -52,6 +52,43 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
   }
 }
 
+// Resolves the evaluation's shape (split count S, tile count, row stride of
+// the partial buffers), this workgroup's (split, first compact column j0) and
+// the plan behind each of its kPT columns (-1: empty), and stages the
+// columns' structure weights.  Returns false, for the whole workgroup, when
+// the grid is larger than this round's S * ntiles.
+__device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, float* sW, int& s, int& S,
+                                  int& stride, int& j0) {
+  int ntiles, nact;
+  if (a.rt != nullptr) {
+    const RoundTable rt = *a.rt;
+    S = rt.S;
+    ntiles = rt.ntiles;
+    nact = rt.nact;
+    stride = rt.ntiles * kPT;
+  } else {
+    S = a.S;
+    ntiles = a.ntiles;
+    nact = a.Pp;
+    stride = a.Pp;
+  }
+  if ((int)blockIdx.x >= S * ntiles) return false;
+  int tile;
+  split_tile(blockIdx.x, S, ntiles, s, tile);
+  j0 = tile * kPT;
+  const int tid = threadIdx.x;
+  if (tid < kPT) {
+    const int j = j0 + tid;
+    sPlan[tid] = j < nact ? (a.act != nullptr ? a.act[j] : j) : -1;
+  }
+  __syncthreads();
+  for (int i = tid; i < kPT * kGmax; i += 256) {
+    const int pl = sPlan[i / kGmax];
+    sW[i] = pl >= 0 ? a.wn[(size_t)pl * kGmax + (i % kGmax)] : 0.f;
+  }
+  return true;
+}
+
 // MODE_F32    : FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4_f32).
 // MODE_ACC64  : FP32 operands, the dose accumulated in FP64
 //               (v_mfma_f64_16x16x4_f64) and the penalty evaluated in FP64.
@@ -71,6 +108,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
 
   __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
   __shared__ float sW[kPT * kGmax];
+  __shared__ int sPlan[kPT];
   __shared__ float4 sP[kGmax + 1];
   __shared__ double sP64[kGmax + 1][4];
   __shared__ int sG[2][kBM];
@@ -81,19 +119,8 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   const int q = lane >> 4;
   const int n = lane & 15;
 
-  int s, tile;
-  split_tile(blockIdx.x, a.S, a.ntiles, s, tile);
-  const int p0 = tile * kPT;
-
-  // Skip tiles whose plans have all stopped.
-  if (a.ps != nullptr) {
-    int act = 0;
-    if (tid < kPT) act = state_active(a.ps[p0 + tid].status) ? 1 : 0;
-    if (!__syncthreads_or(act)) return;
-  }
-  if (a.work != nullptr && tid == 0) atomicAdd(a.work, 1ull);
-
-  for (int i = tid; i < kPT * kGmax; i += 256) sW[i] = a.wn[(size_t)p0 * kGmax + i];
+  int s, S, stride, j0;
+  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -102,26 +129,28 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
       for (int c = 0; c < 4; ++c) sP64[j][c] = a.gt.prm64[j][c];
     }
 
-  const int plan = p0 + wave * 16 + n;
-  const float* __restrict__ xrow = a.x + (size_t)plan * KP;
+  const int col = wave * 16 + n;
+  const int plan = sPlan[col];
+  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
   // B operand of the dose product: lane (q, n) holds t = x^2 of plan n at
   // dwells 16 k + 4 q + j (j = 0..3) for slice k.
   float tf[KP / 4];
 #pragma unroll
   for (int k = 0; k < NK16; ++k) {
     const float4 xv = *reinterpret_cast<const float4*>(xrow + 16 * k + 4 * q);
-    tf[4 * k + 0] = xv.x * xv.x;
-    tf[4 * k + 1] = xv.y * xv.y;
-    tf[4 * k + 2] = xv.z * xv.z;
-    tf[4 * k + 3] = xv.w * xv.w;
+    tf[4 * k + 0] = pv ? xv.x * xv.x : 0.f;
+    tf[4 * k + 1] = pv ? xv.y * xv.y : 0.f;
+    tf[4 * k + 2] = pv ? xv.z * xv.z : 0.f;
+    tf[4 * k + 3] = pv ? xv.w * xv.w : 0.f;
   }
   f4v gacc[NK16];
 #pragma unroll
   for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
   double facc = 0.0;
 
-  const int b_begin = (int)(((long long)s * a.nblocks) / a.S);
-  const int b_end = (int)(((long long)(s + 1) * a.nblocks) / a.S);
+  const int b_begin = (int)(((long long)s * a.nblocks) / S);
+  const int b_end = (int)(((long long)(s + 1) * a.nblocks) / S);
   const f4v* __restrict__ Dg = reinterpret_cast<const f4v*>(a.D);
 
   // Software pipeline over 16-point blocks with two LDS buffers: while the
@@ -278,7 +307,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
 #undef GMCO_STAGE
 
   // ---- write split partials ----
-  float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
+  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
 #pragma unroll
   for (int k = 0; k < NK16; ++k) {
     *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
@@ -286,7 +315,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   }
   facc += __shfl_xor(facc, 16);
   facc += __shfl_xor(facc, 32);
-  if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
+  if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +350,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   __shared__ __attribute__((aligned(16))) __bf16 sD[BMP * DS];
   __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
   __shared__ float sW[kPT * kGmax];
+  __shared__ int sPlan[kPT];
   __shared__ float4 sP[kGmax + 1];
   __shared__ int sG[BMP];
 
@@ -329,36 +359,30 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int n = lane & 15;
-  int s, tile;
-  split_tile(blockIdx.x, a.S, a.ntiles, s, tile);
-  const int p0 = tile * kPT;
-  if (a.ps != nullptr) {
-    int act = 0;
-    if (tid < kPT) act = state_active(a.ps[p0 + tid].status) ? 1 : 0;
-    if (!__syncthreads_or(act)) return;
-  }
-  if (a.work != nullptr && tid == 0) atomicAdd(a.work, 1ull);
-  for (int i = tid; i < kPT * kGmax; i += 256) sW[i] = a.wn[(size_t)p0 * kGmax + i];
+  int s, S, stride, j0;
+  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];
 
-  const int plan = p0 + wave * 16 + n;
-  const float* __restrict__ xrow = a.x + (size_t)plan * KP;
+  const int col = wave * 16 + n;
+  const int plan = sPlan[col];
+  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
   // B operand of the dose product: t = x^2 of plan n at dwells 32 k + 8 q + e
   bf8v tb[NK32];
 #pragma unroll
   for (int k = 0; k < NK32; ++k) {
     const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
     const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
-    tb[k][0] = (__bf16)(x0.x * x0.x);
-    tb[k][1] = (__bf16)(x0.y * x0.y);
-    tb[k][2] = (__bf16)(x0.z * x0.z);
-    tb[k][3] = (__bf16)(x0.w * x0.w);
-    tb[k][4] = (__bf16)(x1.x * x1.x);
-    tb[k][5] = (__bf16)(x1.y * x1.y);
-    tb[k][6] = (__bf16)(x1.z * x1.z);
-    tb[k][7] = (__bf16)(x1.w * x1.w);
+    tb[k][0] = (__bf16)(pv ? x0.x * x0.x : 0.f);
+    tb[k][1] = (__bf16)(pv ? x0.y * x0.y : 0.f);
+    tb[k][2] = (__bf16)(pv ? x0.z * x0.z : 0.f);
+    tb[k][3] = (__bf16)(pv ? x0.w * x0.w : 0.f);
+    tb[k][4] = (__bf16)(pv ? x1.x * x1.x : 0.f);
+    tb[k][5] = (__bf16)(pv ? x1.y * x1.y : 0.f);
+    tb[k][6] = (__bf16)(pv ? x1.z * x1.z : 0.f);
+    tb[k][7] = (__bf16)(pv ? x1.w * x1.w : 0.f);
   }
   f4v gacc[NK16];
 #pragma unroll
@@ -366,8 +390,8 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   double facc = 0.0;
 
   const int nb = a.Mp / BMP;
-  const int b_begin = (int)(((long long)s * nb) / a.S);
-  const int b_end = (int)(((long long)(s + 1) * nb) / a.S);
+  const int b_begin = (int)(((long long)s * nb) / S);
+  const int b_end = (int)(((long long)(s + 1) * nb) / S);
   const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
   const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
 
@@ -450,7 +474,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   }
 #undef GMCO_PF16
 
-  float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
+  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
 #pragma unroll
   for (int k = 0; k < NK16; ++k) {
     *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
@@ -458,7 +482,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   }
   facc += __shfl_xor(facc, 16);
   facc += __shfl_xor(facc, 32);
-  if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
+  if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
 }
 
 // ---------------------------------------------------------------------------
@@ -494,6 +518,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char sD[BMP * DS];
   __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
   __shared__ float sW[kPT * kGmax];
+  __shared__ int sPlan[kPT];
   __shared__ float4 sP[kGmax + 1];
   __shared__ int sG[BMP];
 
@@ -502,22 +527,16 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int n = lane & 15;
-  int s, tile;
-  split_tile(blockIdx.x, a.S, a.ntiles, s, tile);
-  const int p0 = tile * kPT;
-  if (a.ps != nullptr) {
-    int act = 0;
-    if (tid < kPT) act = state_active(a.ps[p0 + tid].status) ? 1 : 0;
-    if (!__syncthreads_or(act)) return;
-  }
-  if (a.work != nullptr && tid == 0) atomicAdd(a.work, 1ull);
-  for (int i = tid; i < kPT * kGmax; i += 256) sW[i] = a.wn[(size_t)p0 * kGmax + i];
+  int s, S, stride, j0;
+  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];
 
-  const int plan = p0 + wave * 16 + n;
-  const float* __restrict__ xrow = a.x + (size_t)plan * KP;
+  const int col = wave * 16 + n;
+  const int plan = sPlan[col];
+  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
   // scaled dwell times t_l s_l, their per-plan maximum, then FP8 and BF16 fragments
   float ts[NK32][8];
   float tmax = 0.f;
@@ -527,7 +546,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
     for (int e = 0; e < 8; ++e) {
       const int l = 32 * k + 8 * q + e;
       const float xv = xrow[l];
-      ts[k][e] = xv * xv * a.colscale[l];
+      ts[k][e] = pv ? xv * xv * a.colscale[l] : 0.f;
       tmax = fmaxf(tmax, ts[k][e]);
     }
   }
@@ -548,8 +567,8 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   double facc = 0.0;
 
   const int nb = a.Mp / BMP;
-  const int b_begin = (int)(((long long)s * nb) / a.S);
-  const int b_end = (int)(((long long)(s + 1) * nb) / a.S);
+  const int b_begin = (int)(((long long)s * nb) / S);
+  const int b_end = (int)(((long long)(s + 1) * nb) / S);
   const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
   const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
 
@@ -640,7 +659,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   }
 #undef GMCO_PF8
 
-  float* __restrict__ gout = a.Gpart + ((size_t)s * a.Pp + plan) * KP;
+  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
 #pragma unroll
   for (int k = 0; k < NK16; ++k) {
     *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
@@ -648,12 +667,13 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   }
   facc += __shfl_xor(facc, 16);
   facc += __shfl_xor(facc, 32);
-  if (q == 0) a.Fpart[(size_t)s * a.Pp + plan] = facc;
+  if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
 }
 
 template <int KP>
 hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
-  const dim3 grid(a.S * a.ntiles), block(256);
+  if (a.grid < 1) return hipErrorInvalidValue;
+  const dim3 grid(a.grid), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_ACC64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)

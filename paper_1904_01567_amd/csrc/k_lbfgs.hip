@@ -62,21 +62,19 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
     g[j] = valid[j] ? a.g[row + e] : 0.f;
     d[j] = valid[j] ? a.dir[row + e] : 0.f;
   }
-  for (int s0 = 0; s0 < a.S; s0 += 8) {
+  // gradient partials of this round's compact column, summed by k_reduce_g
+  const RoundTable rt = *a.rt;
+  const size_t stride = (size_t)rt.ntiles * kPT;
+  const size_t col = (size_t)a.slot[p];
+  {
+    const float* src = a.Gsum + col * Kp;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int s = s0 + u;
-      if (s < a.S) {
-        const float* src = a.Gpart + ((size_t)s * a.Pp + p) * Kp;
-#pragma unroll
-        for (int j = 0; j < E; ++j)
-          if (valid[j]) G[j] += src[lane + 64 * j];
-      }
-    }
+    for (int j = 0; j < E; ++j)
+      if (valid[j]) G[j] = src[lane + 64 * j];
   }
   // split partials of F: one load per lane, then a fixed-order wave sum
   double fpart = 0.0;
-  for (int s = lane; s < a.S; s += 64) fpart += a.Fpart[(size_t)s * a.Pp + p];
+  for (int s = lane; s < rt.S; s += 64) fpart += a.Fpart[s * stride + col];
   const double Ft = wave_sum(fpart);
 #pragma unroll
   for (int j = 0; j < E; ++j) gt[j] = 4.f * xt[j] * G[j];
@@ -296,6 +294,102 @@ hipError_t launch_update_e(const UpdateArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Sum of the split-M gradient partials of every compact column, in split
+// order: one thread per (column, 4 dwells), so the sum has the whole chip's
+// parallelism however many splits a round uses.
+__global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpart, const RoundTable* rt,
+                                                  int Kp, float* __restrict__ Gsum) {
+  const RoundTable r = *rt;
+  const int nq = Kp / 4;
+  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int j = (int)(idx / nq);
+  const int c = (int)(idx - (long long)j * nq);
+  if (j >= r.nact) return;
+  const size_t stride = (size_t)r.ntiles * kPT * Kp;
+  const float4* src = reinterpret_cast<const float4*>(Gpart + (size_t)j * Kp) + c;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  int s = 0;
+  for (; s + 8 <= r.S; s += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(s + u) * stride / 4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc.x += v[u].x;
+      acc.y += v[u].y;
+      acc.z += v[u].z;
+      acc.w += v[u].w;
+    }
+  }
+  for (; s < r.S; ++s) {
+    const float4 v = src[s * stride / 4];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  reinterpret_cast<float4*>(Gsum + (size_t)j * Kp)[c] = acc;
+}
+
+// Active-plan compaction, one workgroup before every evaluation: lists the
+// plans still running in plan order (act), gives each its compact column
+// (slot, -1 when stopped), and sets the round's tile and split counts so that
+// the evaluation covers only ceil(nact / kPT) tiles, split to fill the chip.
+// A tuned split applies while every tile of the batch is active.
+constexpr int kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(const PlanState* __restrict__ ps, int P,
+                                                             int nblocks, int n_cu, int s_tuned,
+                                                             int ntiles_full, int* __restrict__ act,
+                                                             int* __restrict__ slot, RoundTable* rt,
+                                                             unsigned long long* work) {
+  __shared__ int wsum[kCompactThreads / 64];
+  __shared__ int total;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int per = (P + kCompactThreads - 1) / kCompactThreads;
+  const int b = t * per;
+  const int e = min(b + per, P);
+  int cnt = 0;
+  for (int p = b; p < e; ++p) cnt += state_active(ps[p].status) ? 1 : 0;
+  int v = cnt;  // inclusive scan over the wavefront
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) wsum[wave] = v;
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int w = 0; w < kCompactThreads / 64; ++w) {
+      const int x = wsum[w];
+      wsum[w] = acc;
+      acc += x;
+    }
+    total = acc;
+  }
+  __syncthreads();
+  int off = wsum[wave] + v - cnt;
+  for (int p = b; p < e; ++p) {
+    if (state_active(ps[p].status)) {
+      act[off] = p;
+      slot[p] = off++;
+    } else {
+      slot[p] = -1;
+    }
+  }
+  if (t == 0) {
+    RoundTable r;
+    r.nact = total;
+    r.ntiles = (total + kPT - 1) / kPT;
+    r.S = (s_tuned > 0 && r.ntiles == ntiles_full) ? s_tuned : choose_split(r.ntiles, nblocks, n_cu, kSplitMax);
+    r.pad = 0;
+    *rt = r;
+    if (work != nullptr) *work += (unsigned long long)total;
+  }
+}
+
 // Partial reduction for a stand-alone evaluation: F = sum_s Fpart, g = 4 x G.
 __global__ void k_finish_eval(const float* __restrict__ Gpart, const double* __restrict__ Fpart,
                               const float* __restrict__ x, int S, int P, int Pp, int K, int Kp,
@@ -350,6 +444,23 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t st) {
     case 8: return launch_update_e<8>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_compact(const PlanState* ps, int P, int nblocks, int n_cu, int s_tuned,
+                          int ntiles_full, int* act, int* slot, RoundTable* rt,
+                          unsigned long long* work, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, ps, P, nblocks, n_cu, s_tuned,
+                     ntiles_full, act, slot, rt, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
+                           hipStream_t st) {
+  if (Kp % 4 != 0) return hipErrorInvalidValue;
+  const long long threads = (long long)Pp * (Kp / 4);
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  hipLaunchKernelGGL(k_reduce_g, grid, dim3(256), 0, st, Gpart, rt, Kp, Gsum);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
