@@ -34,6 +34,16 @@ TOL_V100 = 0.1      # target V100 difference in percentage points
 # Accepted L-BFGS steps per plan after which every checked plan of the
 # workload meets both tolerances (calibrated with --calibrate against the
 # oracle optima in tests/golden/c2_reference_optima.json).
+TIME_EVERY = 16  # rounds between timed rounds in the timed steps
+
+# HBM bytes per full-batch launch of the FP64-accumulating evaluation kernel on
+# the 360 x 20,000 x 1,000 workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, median of the full-batch dispatches) scaled by the same
+# counters on a 256 MiB copy (read x 2.000, write x 1.000); valid only for the
+# kernel source they were taken on (first 16 hex digits of its SHA-256).
+EVAL_TRAFFIC = {"k_eval_sha256": "b05f096a013c0ed6", "dtype": "f32acc64", "plans": 1000,
+                "fetch_kib": 21305.4, "fetch_scale": 262144.0 / 131092.5,
+                "write_kib": 24747.5, "write_scale": 262144.0 / 262144.0}
 ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
 # MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
 PEAK_F64 = 78.6
@@ -110,6 +120,19 @@ def cpu_baseline(n_plans: int, n_iters: int, iters_full: int):
                        f"{threads}), scaled to {iters_full} iterations per plan")
 
 
+def eval_traffic(dtype: str, plans: int):
+    """Counter-derived HBM bytes per launch, or None when the kernel source,
+    the arithmetic or the batch differs from the one the counters were taken on."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_01567_amd", "csrc", "k_eval.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    t = EVAL_TRAFFIC
+    if sha != t["k_eval_sha256"] or dtype != t["dtype"] or plans != t["plans"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def eps_sweep(args) -> int:
     """Stop rule trade-off (Sec. 2.2.4 and Fig. 3a of the paper): relative
     objective variation eps against time and the non-dominated fraction."""
@@ -134,7 +157,7 @@ def eps_sweep(args) -> int:
         best, cls, nd, frac = pl.select_plan()
         # kernel split of the same run, timed separately (events add overhead)
         pl.set_weights(W)
-        tk = pl.optimize(max_iter=args.iters or 20000, eps=eps, time_kernels=True)
+        tk = pl.optimize(max_iter=args.iters or 20000, eps=eps, time_kernels=1)
         m = pl.metrics()
         rep = tolerance_report(m, golden)
         rows.append({"eps": eps, "seconds": dt, "rounds": info["rounds"],
@@ -385,14 +408,15 @@ def main(argv=None) -> int:
             print(json.dumps({"iters": n, "info": info, "tol": rep}), flush=True)
         return 0
 
-    def step(time_kernels=False):
+    def step(time_kernels=0):
         pl.set_weights(W)
         infos = []
         for k, (dt, cap) in enumerate(stages):
             infos.append(pl.optimize(max_iter=cap, time_kernels=time_kernels, dtype=dt,
                                      resume_stopped=k > 0))
         info = {key: sum(i[key] for i in infos) for key in
-                ("rounds", "device_ms", "eval_ms", "update_ms", "eval_launches", "eval_work")}
+                ("rounds", "device_ms", "eval_ms", "update_ms", "eval_launches", "eval_work",
+                 "timed_launches", "timed_work")}
         info["stages"] = infos
         t = pl.dwell_times()
         m = pl.metrics()
@@ -405,7 +429,7 @@ def main(argv=None) -> int:
     infos = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        info, t, m = step(time_kernels=True)
+        info, t, m = step(time_kernels=TIME_EVERY)
         infos.append(info)
         print(f"# step {k + 1}/{args.steps}: {info['rounds']} rounds, "
               f"{info['device_ms']:.1f} ms device", file=sys.stderr, flush=True)
@@ -417,10 +441,12 @@ def main(argv=None) -> int:
     # roofline of the fused evaluation kernel of the last (dominant) stage
     M, K, P = case.M, case.K, args.plans
     flops_full = 4.0 * M * K * P          # dose product + back-projection, unpadded
+    # HIP events around every TIME_EVERY-th round's launches (sampled, so the
+    # events barely perturb the timed run); the timed launches' own work
     last = [i["stages"][-1] for i in infos]
     eval_ms = sum(i["eval_ms"] for i in last)
-    launches = sum(i["eval_launches"] for i in last)
-    work = sum(i["eval_work"] for i in last)
+    launches = sum(i["timed_launches"] for i in last)
+    work = sum(i["timed_work"] for i in last)
     achieved = work * flops_full / (eval_ms / 1e3) / 1e12
     peak = eval_peak_tflops(stages[-1][0])
     tol = tolerance_report(m, golden)
@@ -448,9 +474,10 @@ def main(argv=None) -> int:
             "lbfgs_history": 10, "stages": [f"{d}:{n}" for d, n in stages],
         },
         "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
-        "breakdown_ms_per_step": {
-            "eval_kernels": sum(i["eval_ms"] for i in infos) / args.steps,
-            "update_kernels": upd_ms / args.steps,
+        "breakdown_per_step": {
+            "eval_us_per_launch": 1e3 * sum(i["eval_ms"] for i in infos) / max(1, sum(i["timed_launches"] for i in infos)),
+            "reduce_update_us_per_round": 1e3 * upd_ms / max(1, sum(i["timed_launches"] for i in infos)),
+            "timed_rounds": sum(i["timed_launches"] for i in infos) / args.steps,
             "rounds": sum(i["rounds"] for i in infos) / args.steps,
             "rounds_per_stage": [sum(i["stages"][k]["rounds"] for i in infos) / args.steps
                                  for k in range(len(stages))],
@@ -464,8 +491,10 @@ def main(argv=None) -> int:
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "avg_launch_us": 1e3 * eval_ms / max(1, launches),
-            "full_launch_equivalents": work,
-            "traffic": None,
+            "timed_launches": launches,
+            "timed_full_launch_equivalents": work,
+            "traffic": eval_traffic(stages[-1][0], P),
+            "traffic_unit": "HBM bytes per full-batch launch (rocprofv3 counters, copy-scaled)",
         },
     }
     if not args.no_cpu_baseline:

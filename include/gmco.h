@@ -111,7 +111,8 @@ typedef struct {
   double beta;        /* backtracking factor in (0, 1), e.g. 0.5 */
   int max_ls;         /* trials per iteration before LS_FAIL, >= 1 */
   int check_every;    /* rounds between host checks of the active-plan count (0 -> 16) */
-  int time_kernels;   /* 1: time every evaluation and update launch with HIP events */
+  int time_kernels;   /* n > 0: time the evaluation and the update launches of rounds
+                         0, n, 2n, ... with HIP events on the context stream; 0: none */
   int resume_stopped; /* 1: plans stopped as CONVERGED or LS_FAIL iterate again
                          (e.g. after a change of precision); 0: they stay */
   int dtype;          /* gmco_dtype of this run's evaluations, -1: the context's.
@@ -129,12 +130,14 @@ typedef struct {
   int n_nonfinite;
   int max_iters;       /* largest accepted-step count of any plan */
   float device_ms;     /* GPU time of the whole run (HIP events on the context stream) */
-  float eval_ms;       /* sum of evaluation-kernel durations (time_kernels = 1) */
-  float update_ms;     /* sum of L-BFGS update-kernel durations (time_kernels = 1) */
+  float eval_ms;       /* sum of the timed evaluation-kernel durations */
+  float update_ms;     /* sum of the timed split-reduction + L-BFGS update durations */
   int eval_launches;   /* evaluation launches */
   double eval_work;    /* plan evaluations done / batch size: full-batch launch
                           equivalents (stopped plans are compacted out of every
                           evaluation) */
+  int timed_launches;  /* evaluation launches timed (time_kernels > 0) */
+  double timed_work;   /* plan evaluations of the timed launches / batch size */
 } gmco_run_info;
 
 typedef struct {

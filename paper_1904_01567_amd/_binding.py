@@ -73,7 +73,8 @@ class gmco_run_info(C.Structure):
     _fields_ = [("rounds", C.c_int), ("n_converged", C.c_int), ("n_maxiter", C.c_int),
                 ("n_ls_fail", C.c_int), ("n_nonfinite", C.c_int), ("max_iters", C.c_int),
                 ("device_ms", C.c_float), ("eval_ms", C.c_float), ("update_ms", C.c_float),
-                ("eval_launches", C.c_int), ("eval_work", C.c_double)]
+                ("eval_launches", C.c_int), ("eval_work", C.c_double),
+                ("timed_launches", C.c_int), ("timed_work", C.c_double)]
 
 
 class gmco_plan_metrics(C.Structure):
@@ -265,10 +266,10 @@ class Planner:
         return F, g
 
     def optimize(self, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
-                 max_ls: int = 30, check_every: int = 16, time_kernels: bool = False,
+                 max_ls: int = 30, check_every: int = 16, time_kernels: int = 0,
                  resume_stopped: bool = False, dtype: Optional[str] = None) -> dict:
         r = gmco_run(int(max_iter), float(eps), float(c1), float(beta), int(max_ls),
-                     int(check_every), int(bool(time_kernels)), int(bool(resume_stopped)),
+                     int(check_every), int(time_kernels), int(bool(resume_stopped)),
                      -1 if dtype is None else DTYPES[dtype], 0)
         info = gmco_run_info()
         self._check(self.lib.gmco_optimize(self._ctx, C.byref(r), C.byref(info)), "optimize")

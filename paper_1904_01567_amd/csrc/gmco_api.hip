@@ -22,7 +22,8 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t Wst, t0st, xst, Fst, gst;
-  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, act, slot, rt;
+  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, flag, slot, rt,
+      split_tab;
   size_t t64, d64, metrics, hist, feat, sel;
   size_t total;
 };
@@ -33,9 +34,34 @@ struct Dims {
   int S_tuned = 0;    // split set by the caller or the autotuner, 0 = heuristic
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
   int grid_cap = 1;   // workgroups (of kPT columns) the partial buffers hold
+  // split count per active tile count 0..ntiles, for 16-point (FP32 modes)
+  // and 32-point (BF16, FP8) evaluation blocks
+  std::vector<int> split16, split32;
 };
 
 constexpr int kSplitTuneMax = 32;
+
+// Split count for ntiles plan tiles over nblocks point blocks on n_cu compute
+// units (one evaluation workgroup per CU at a time): minimises the number of
+// workgroup waves times the blocks per workgroup (plus a pipeline fill of two
+// blocks), with a slight preference for multiples of 8 (the XCD-aware tile
+// mapping of the evaluation kernel).
+int choose_split(int ntiles, int nblocks, int n_cu, int s_max) {
+  if (ntiles <= 0 || nblocks <= 0) return 1;
+  const int hi = std::min(s_max, nblocks);
+  int best = 1;
+  double best_c = 0.0;
+  for (int S = 1; S <= hi; ++S) {
+    const double waves = (double)(((long long)ntiles * S + n_cu - 1) / n_cu);
+    const double per = (double)((nblocks + S - 1) / S + 2);
+    const double c = waves * per * ((S & 7) ? 1.02 : 1.0);
+    if (S == 1 || c < best_c) {
+      best_c = c;
+      best = S;
+    }
+  }
+  return best;
+}
 
 }  // namespace
 
@@ -114,10 +140,12 @@ Dims make_dims(int M, int K, int Pmax, int n_cu) {
   // compacted rounds choose their split on the device for 1..ntiles active
   // tiles, with the 16-point (FP32) or 32-point (BF16, FP8) block count
   d.grid_heur = 1;
+  d.split16.assign(d.ntiles + 1, 1);
+  d.split32.assign(d.ntiles + 1, 1);
   for (int nt = 1; nt <= d.ntiles; ++nt) {
-    const int s16 = choose_split(nt, d.nblocks, n_cu, kSplitMax);
-    const int s32 = choose_split(nt, d.Mp / 32, n_cu, kSplitMax);
-    d.grid_heur = std::max(d.grid_heur, nt * std::max(s16, s32));
+    d.split16[nt] = choose_split(nt, d.nblocks, n_cu, kSplitMax);
+    d.split32[nt] = choose_split(nt, d.Mp / 32, n_cu, kSplitMax);
+    d.grid_heur = std::max(d.grid_heur, nt * std::max(d.split16[nt], d.split32[nt]));
   }
   d.grid_cap = std::max(d.grid_heur, d.ntiles * d.S_cap);
   return d;
@@ -166,11 +194,12 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.Gpart = take((size_t)d.grid_cap * kPT * d.Kp * 4);
   L.Fpart = take((size_t)d.grid_cap * kPT * 8);
   L.Gsum = take(PK * 4);
-  L.act = take((size_t)d.Pp * 4);
+  L.flag = take((size_t)d.Pp * 4);
   L.slot = take((size_t)d.Pp * 4);
   L.rt = take(sizeof(RoundTable));
+  L.split_tab = take((size_t)2 * (d.ntiles + 1) * 4);
   L.active = take(2 * sizeof(int));
-  L.work = take(sizeof(unsigned long long));
+  L.work = take(2 * sizeof(unsigned long long));
   L.t64 = take(PK * 8);
   // final doses (Pp x Mp); an FP8 context also widens its matrix (Mp x Kp) here
   L.d64 = take((size_t)std::max(d.Pp, dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp * 8);
@@ -195,13 +224,8 @@ int copy_h2d(gmco_ctx* c, void* dst, const void* src, size_t bytes) {
   return GMCO_OK;
 }
 
-// Point blocks over which a compacted round splits, for the kernel of dtype.
-int split_blocks(const gmco_ctx* c, int dtype) {
-  return is_low_precision(dtype) ? c->dim.Mp / 32 : c->dim.nblocks;
-}
-
-// compacted: the active-plan list and round table written by k_compact
-// decide the columns and the split; otherwise every plan, host split.
+// compacted: the evaluation ranks the running plans itself and decides the
+// round's tiles and split; otherwise every plan, host split.
 EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype) {
   EvalArgs a{};
   a.D = is_low_precision(dtype) ? c->at<void>(c->lay.Dlp) : c->at<void>(c->lay.D32);
@@ -210,8 +234,15 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.grp = c->at<int>(c->lay.grp);
   a.x = x;
   a.wn = c->at<float>(c->lay.wn);
-  a.act = compacted ? c->at<int>(c->lay.act) : nullptr;
-  a.rt = compacted ? c->at<RoundTable>(c->lay.rt) : nullptr;
+  if (compacted) {
+    a.flag = c->at<int>(c->lay.flag);
+    a.split_tab = c->at<int>(c->lay.split_tab) + (is_low_precision(dtype) ? c->dim.ntiles + 1 : 0);
+    a.slot = c->at<int>(c->lay.slot);
+    a.rt = c->at<RoundTable>(c->lay.rt);
+    a.work = c->at<unsigned long long>(c->lay.work);
+    a.P = c->P;
+    a.s_tuned = c->dim.S_tuned;
+  }
   a.Gpart = c->at<float>(c->lay.Gpart);
   a.Fpart = c->at<double>(c->lay.Fpart);
   a.Mp = c->dim.Mp;
@@ -223,13 +254,6 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.grid = compacted ? std::max(c->dim.grid_heur, c->dim.ntiles * c->dim.S_tuned) : a.S * a.ntiles;
   a.gt = c->gt;
   return a;
-}
-
-hipError_t launch_compact_ctx(const gmco_ctx* c, int dtype, hipStream_t st) {
-  const Layout& L = c->lay;
-  return launch_compact(c->at<PlanState>(L.ps), c->P, split_blocks(c, dtype), c->n_cu, c->dim.S_tuned,
-                        c->dim.ntiles, c->at<int>(L.act), c->at<int>(L.slot), c->at<RoundTable>(L.rt),
-                        c->at<unsigned long long>(L.work), st);
 }
 
 UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
@@ -248,6 +272,7 @@ UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
   u.ps = c->at<PlanState>(L.ps);
   u.active_count = c->at<int>(L.active);
   u.slot = c->at<int>(L.slot);
+  u.flag = c->at<int>(L.flag);
   u.rt = c->at<RoundTable>(L.rt);
   u.Kp = d.Kp;
   u.Pp = d.Pp;
@@ -471,6 +496,10 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   if ((rc = copy_h2d(c, c->at<void>(L.goff), c->offsets.data(), kGmax * 4))) return rc;
   if ((rc = copy_h2d(c, c->at<void>(L.gcnt), counts.data(), kGmax * 4))) return rc;
   if ((rc = copy_h2d(c, c->at<void>(L.counts), counts.data(), kGmax * 4))) return rc;
+  // (host vectors of this call stay alive until the stream synchronisation below)
+  std::vector<int> split_tab(d.split16);
+  split_tab.insert(split_tab.end(), d.split32.begin(), d.split32.end());
+  if ((rc = copy_h2d(c, c->at<void>(L.split_tab), split_tab.data(), split_tab.size() * 4))) return rc;
   for (int j = 0; j <= kGmax; ++j) {
     for (int k = 0; k < 4; ++k) c->gt.prm64[j][k] = j < G ? gp[4 * j + k] : 0.0;
     c->gt.prm[j] = make_float4((float)c->gt.prm64[j][0], (float)c->gt.prm64[j][1],
@@ -545,18 +574,23 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   const Layout& L = c->lay;
   const Dims& d = c->dim;
   int* active = c->at<int>(L.active);
-  unsigned long long* work = c->at<unsigned long long>(L.work);
+  unsigned long long* work = c->at<unsigned long long>(L.work);  // [0] all launches, [1] timed ones
   GMCO_HIP(c, hipMemsetAsync(active, 0, 2 * sizeof(int), c->stream));
-  GMCO_HIP(c, hipMemsetAsync(work, 0, sizeof(unsigned long long), c->stream));
-  GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), d.Pp, d.Kp,
+  GMCO_HIP(c, hipMemsetAsync(work, 0, 2 * sizeof(unsigned long long), c->stream));
+  GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), c->at<int>(L.flag), d.Pp, d.Kp,
                             r->max_iter, r->resume_stopped, c->stream));
   UpdateArgs u = update_args(c, r);
   EvalArgs a = eval_args(c, c->at<float>(L.xt), true, dtype);
+  EvalArgs a_timed = a;  // the timed launches also count their work apart
+  a_timed.work2 = work + 1;
   const int check = r->check_every > 0 ? r->check_every : 16;
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
-  // optional per-launch timing: 4 events per round of one check block
+  // optional sampled timing: events around the evaluation and the update of
+  // every time_kernels-th round, 4 per timed round of one check block
+  const int every = r->time_kernels;
   std::vector<hipEvent_t> ev;
-  if (r->time_kernels) {
+  int timed = 0;
+  if (every > 0) {
     ev.resize((size_t)4 * check, nullptr);
     for (auto& e : ev) {
       if (hipEventCreate(&e) != hipSuccess) {
@@ -575,6 +609,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   } guard{ev};
   double eval_ms = 0.0, update_ms = 0.0;
   auto harvest = [&](int n) -> hipError_t {
+    timed += n;
     for (int i = 0; i < n; ++i) {
       float a_ms = 0.f, b_ms = 0.f;
       hipError_t e = hipEventElapsedTime(&a_ms, ev[4 * i], ev[4 * i + 1]);
@@ -591,21 +626,23 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   int in_block = 0;
   for (; round < max_rounds; ++round) {
     u.round = (int)round;
-    GMCO_HIP(c, launch_compact_ctx(c, dtype, c->stream));
-    if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
-    GMCO_HIP(c, launch_eval(a, dtype, c->stream));
-    if (r->time_kernels) {
+    const bool tk = every > 0 && round % every == 0;
+    if (tk) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
+    GMCO_HIP(c, launch_eval(tk ? a_timed : a, dtype, c->stream));
+    if (tk) {
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 1], c->stream));
       GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 2], c->stream));
     }
     GMCO_HIP(c, launch_reduce_g(a.Gpart, a.rt, d.Pp, d.Kp, c->at<float>(L.Gsum), c->stream));
     GMCO_HIP(c, launch_update(u, c->stream));
-    if (r->time_kernels) GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 3], c->stream));
-    ++in_block;
+    if (tk) {
+      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 3], c->stream));
+      ++in_block;
+    }
     if ((round + 1) % check == 0) {
       GMCO_HIP(c, hipMemcpyAsync(c->host_count, active + (round & 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
       GMCO_HIP(c, hipStreamSynchronize(c->stream));
-      if (r->time_kernels) GMCO_HIP(c, harvest(in_block));
+      if (every > 0) GMCO_HIP(c, harvest(in_block));
       in_block = 0;
       if (*c->host_count == 0) {
         ++round;
@@ -615,12 +652,17 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   }
   GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
   GMCO_HIP(c, hipEventSynchronize(c->ev1));
-  if (r->time_kernels) GMCO_HIP(c, harvest(in_block));
-  unsigned long long done = 0;
-  GMCO_HIP(c, hipMemcpy(&done, work, sizeof(done), hipMemcpyDeviceToHost));
+  if (every > 0) GMCO_HIP(c, harvest(in_block));
+  unsigned long long done[2] = {0, 0};
+  GMCO_HIP(c, hipMemcpy(done, work, sizeof(done), hipMemcpyDeviceToHost));
   float ms = 0.f;
   GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  return summarize(c, round, ms, eval_ms, update_ms, done, info);
+  rc = summarize(c, round, ms, eval_ms, update_ms, done[0], info);
+  if (info) {
+    info->timed_launches = timed;
+    info->timed_work = (double)done[1] / (double)c->P;
+  }
+  return rc;
 }
 
 int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run_info* infos,
@@ -653,7 +695,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     const Layout& L = c->lay;
     GMCO_HIP(c, hipMemsetAsync(c->at<int>(L.active), 0, 2 * sizeof(int), st));
     GMCO_HIP(c, hipMemsetAsync(c->at<unsigned long long>(L.work), 0, sizeof(unsigned long long), st));
-    GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), c->dim.Pp,
+    GMCO_HIP(c, launch_resume(c->at<PlanState>(L.ps), c->at<float>(L.x), c->at<float>(L.xt), c->at<int>(L.flag), c->dim.Pp,
                               c->dim.Kp, r->max_iter, r->resume_stopped, st));
     us[i] = update_args(c, r);
     as[i] = eval_args(c, c->at<float>(L.xt), true, dtypes[i]);
@@ -662,7 +704,6 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
   auto issue_round = [&](long long rd) -> int {
     for (int i = 0; i < n; ++i) {
       us[i].round = (int)rd;
-      GMCO_HIP(ctxs[i], launch_compact_ctx(ctxs[i], dtypes[i], st));
       GMCO_HIP(ctxs[i], launch_eval(as[i], dtypes[i], st));
       GMCO_HIP(ctxs[i], launch_reduce_g(as[i].Gpart, as[i].rt, ctxs[i]->dim.Pp, ctxs[i]->dim.Kp, ctxs[i]->at<float>(ctxs[i]->lay.Gsum), st));
       GMCO_HIP(ctxs[i], launch_update(us[i], st));

@@ -52,36 +52,15 @@ struct GroupTable {
   double prm64[kGmax + 1][4];
 };
 
-// Per-round shape of the compacted evaluation, written on the device before
-// each evaluation: the active plans occupy compact columns 0..nact-1, which
-// form ntiles tiles of kPT; every tile is split S ways over the points.
+// Per-round shape of the compacted evaluation, written by the evaluation
+// kernel: the running plans occupy compact columns 0..nact-1, which form
+// ntiles tiles of kPT; every tile is split S ways over the points.
 struct RoundTable {
   int nact;
   int ntiles;
   int S;
   int pad;
 };
-
-// Split count for ntiles plan tiles over nblocks point blocks on n_cu compute
-// units (one workgroup per CU at a time): minimises the number of workgroup
-// waves times the blocks per workgroup (plus a pipeline fill of two blocks),
-// with a slight preference for multiples of 8 (the XCD-aware tile mapping).
-__host__ __device__ inline int choose_split(int ntiles, int nblocks, int n_cu, int s_max) {
-  if (ntiles <= 0 || nblocks <= 0) return 1;
-  const int hi = s_max < nblocks ? s_max : nblocks;
-  int best = 1;
-  double best_c = 0.0;
-  for (int S = 1; S <= hi; ++S) {
-    const double waves = (double)((ntiles * S + n_cu - 1) / n_cu);
-    const double per = (double)((nblocks + S - 1) / S + 2);
-    const double c = waves * per * ((S & 7) ? 1.02 : 1.0);
-    if (S == 1 || c < best_c) {
-      best_c = c;
-      best = S;
-    }
-  }
-  return best;
-}
 
 struct EvalArgs {
   const void* D;          // [Mp][Kp] dose-rate matrix in the run dtype
@@ -90,12 +69,23 @@ struct EvalArgs {
   const int* grp;         // [Mp] structure index, kGmax for padding
   const float* x;         // [Pp][Kp] points to evaluate (dwell weights)
   const float* wn;        // [Pp][kGmax] w_j / N_j
-  // Compacted rounds: act[j] is the plan in compact column j and rt holds
-  // the round's shape; the partials are then [S][rt.ntiles * kPT][Kp] by
-  // compact column.  Both NULL: every plan, column = plan, host S and
-  // ntiles, partials [S][Pp][Kp].
-  const int* act;
-  const RoundTable* rt;
+  // Compacted rounds (flag != NULL): every workgroup counts the running
+  // plans (flag[p] = 1) in plan order, takes the round's tile count
+  // ntiles = ceil(nact / kPT) and split count split_tab[ntiles] (s_tuned
+  // instead when every tile of the capacity is active), and maps its kPT
+  // columns to the plans of compact ranks j0 .. j0 + kPT - 1.  Split-0
+  // workgroups record each plan's rank in slot; workgroup 0 writes the
+  // round's shape to rt and adds nact to work.  The partials are then
+  // [S][ntiles * kPT][Kp] by rank.  flag == NULL: every plan, column = plan,
+  // host S and ntiles, partials [S][Pp][Kp].
+  const int* flag;
+  const int* split_tab;   // [ntiles + 1] split count per active tile count
+  int* slot;              // [Pp] compact rank of each running plan
+  RoundTable* rt;
+  unsigned long long* work;
+  unsigned long long* work2;  // optional second count (the timed launches)
+  int P;                  // plans of the batch
+  int s_tuned;            // 0 = split_tab
   float* Gpart;           // split-M partial back-projections
   double* Fpart;          // split-M partial objectives
   int Mp, Kp, Pp;
@@ -118,6 +108,7 @@ struct UpdateArgs {
   double* rho;    // [Pp][m]
   PlanState* ps;
   int* active_count;  // [2]
+  int* flag;          // [Pp] 1 while the plan runs, for the next compaction
   const int* slot;    // [Pp] compact column of each active plan
   const RoundTable* rt;
   int Kp, Pp, m, K;
@@ -146,11 +137,8 @@ hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const flo
                               hipStream_t st);
 hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
                            hipStream_t st);
-hipError_t launch_compact(const PlanState* ps, int P, int nblocks, int n_cu, int s_tuned,
-                          int ntiles_full, int* act, int* slot, RoundTable* rt,
-                          unsigned long long* work, hipStream_t st);
-hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int Pp, int Kp, int max_iter,
-                         int resume_stopped, hipStream_t st);
+hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int* flag, int Pp, int Kp,
+                         int max_iter, int resume_stopped, hipStream_t st);
 hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,
                            hipStream_t st);
 hipError_t launch_x_to_device(const double* x_host_dev, int P, int Pp, int K, int Kp, float* xe,

@@ -55,31 +55,70 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
 // Resolves the evaluation's shape (split count S, tile count, row stride of
 // the partial buffers), this workgroup's (split, first compact column j0) and
 // the plan behind each of its kPT columns (-1: empty), and stages the
-// columns' structure weights.  Returns false, for the whole workgroup, when
-// the grid is larger than this round's S * ntiles.
-__device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, float* sW, int& s, int& S,
-                                  int& stride, int& j0) {
-  int ntiles, nact;
-  if (a.rt != nullptr) {
-    const RoundTable rt = *a.rt;
-    S = rt.S;
-    ntiles = rt.ntiles;
-    nact = rt.nact;
-    stride = rt.ntiles * kPT;
-  } else {
-    S = a.S;
-    ntiles = a.ntiles;
-    nact = a.Pp;
-    stride = a.Pp;
-  }
-  if ((int)blockIdx.x >= S * ntiles) return false;
-  int tile;
-  split_tile(blockIdx.x, S, ntiles, s, tile);
-  j0 = tile * kPT;
+// columns' structure weights.  In a compacted round every workgroup ranks
+// the running plans itself (a block-wide scan of the flags), so no separate
+// launch is needed.  Returns false, for the whole workgroup, when the grid
+// is larger than this round's S * ntiles.
+__device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, float* sW, int& s,
+                                  int& S, int& stride, int& j0) {
   const int tid = threadIdx.x;
-  if (tid < kPT) {
-    const int j = j0 + tid;
-    sPlan[tid] = j < nact ? (a.act != nullptr ? a.act[j] : j) : -1;
+  const int lane = tid & 63, wave = tid >> 6;
+  int tile;
+  if (a.flag == nullptr) {
+    S = a.S;
+    stride = a.Pp;
+    if ((int)blockIdx.x >= S * a.ntiles) return false;
+    split_tile(blockIdx.x, S, a.ntiles, s, tile);
+    j0 = tile * kPT;
+    if (tid < kPT) sPlan[tid] = j0 + tid;
+  } else {
+    if (tid < kPT) sPlan[tid] = -1;
+    const int per = (a.P + 255) / 256;
+    const int b = tid * per;
+    const int e = min(b + per, a.P);
+    int cnt = 0;
+    for (int p = b; p < e; ++p) cnt += a.flag[p];
+    int v = cnt;  // inclusive scan over the wavefront, then over the 4 waves
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) sScan[wave] = v;
+    __syncthreads();
+    int base = 0, nact = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int t = sScan[w];
+      base += w < wave ? t : 0;
+      nact += t;
+    }
+    const int ntiles = (nact + kPT - 1) / kPT;
+    S = (a.s_tuned > 0 && ntiles == a.ntiles) ? a.s_tuned : a.split_tab[ntiles];
+    stride = ntiles * kPT;
+    if (blockIdx.x == 0 && tid == 0) {
+      RoundTable r;
+      r.nact = nact;
+      r.ntiles = ntiles;
+      r.S = S;
+      r.pad = 0;
+      *a.rt = r;
+      if (a.work != nullptr) *a.work += (unsigned long long)nact;
+      if (a.work2 != nullptr) *a.work2 += (unsigned long long)nact;
+    }
+    if ((int)blockIdx.x >= S * ntiles) return false;
+    split_tile(blockIdx.x, S, ntiles, s, tile);
+    j0 = tile * kPT;
+    int r = base + v - cnt;
+    for (int p = b; p < e; ++p) {
+      if (a.flag[p]) {
+        if (r >= j0 && r < j0 + kPT) {
+          sPlan[r - j0] = p;
+          if (s == 0) a.slot[p] = r;
+        }
+        ++r;
+      }
+    }
   }
   __syncthreads();
   for (int i = tid; i < kPT * kGmax; i += 256) {
@@ -109,6 +148,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
   __shared__ float sW[kPT * kGmax];
   __shared__ int sPlan[kPT];
+  __shared__ int sScan[4];
   __shared__ float4 sP[kGmax + 1];
   __shared__ double sP64[kGmax + 1][4];
   __shared__ int sG[2][kBM];
@@ -120,7 +160,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   const int n = lane & 15;
 
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
+  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -351,6 +391,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
   __shared__ float sW[kPT * kGmax];
   __shared__ int sPlan[kPT];
+  __shared__ int sScan[4];
   __shared__ float4 sP[kGmax + 1];
   __shared__ int sG[BMP];
 
@@ -360,7 +401,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   const int q = lane >> 4;
   const int n = lane & 15;
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
+  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];
@@ -519,6 +560,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
   __shared__ float sW[kPT * kGmax];
   __shared__ int sPlan[kPT];
+  __shared__ int sScan[4];
   __shared__ float4 sP[kGmax + 1];
   __shared__ int sG[BMP];
 
@@ -528,7 +570,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   const int q = lane >> 4;
   const int n = lane & 15;
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sW, s, S, stride, j0)) return;
+  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];

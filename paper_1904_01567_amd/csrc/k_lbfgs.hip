@@ -280,6 +280,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
   }
   if (lane == 0) {
     a.ps[p] = st;
+    a.flag[p] = state_active(st.status) ? 1 : 0;
     if (state_active(st.status)) atomicAdd(&a.active_count[a.round & 1], 1);
   }
 }
@@ -331,65 +332,6 @@ __global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpar
   reinterpret_cast<float4*>(Gsum + (size_t)j * Kp)[c] = acc;
 }
 
-// Active-plan compaction, one workgroup before every evaluation: lists the
-// plans still running in plan order (act), gives each its compact column
-// (slot, -1 when stopped), and sets the round's tile and split counts so that
-// the evaluation covers only ceil(nact / kPT) tiles, split to fill the chip.
-// A tuned split applies while every tile of the batch is active.
-constexpr int kCompactThreads = 1024;
-
-__global__ __launch_bounds__(kCompactThreads) void k_compact(const PlanState* __restrict__ ps, int P,
-                                                             int nblocks, int n_cu, int s_tuned,
-                                                             int ntiles_full, int* __restrict__ act,
-                                                             int* __restrict__ slot, RoundTable* rt,
-                                                             unsigned long long* work) {
-  __shared__ int wsum[kCompactThreads / 64];
-  __shared__ int total;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int per = (P + kCompactThreads - 1) / kCompactThreads;
-  const int b = t * per;
-  const int e = min(b + per, P);
-  int cnt = 0;
-  for (int p = b; p < e; ++p) cnt += state_active(ps[p].status) ? 1 : 0;
-  int v = cnt;  // inclusive scan over the wavefront
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u = __shfl_up(v, o);
-    if (lane >= o) v += u;
-  }
-  if (lane == 63) wsum[wave] = v;
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int w = 0; w < kCompactThreads / 64; ++w) {
-      const int x = wsum[w];
-      wsum[w] = acc;
-      acc += x;
-    }
-    total = acc;
-  }
-  __syncthreads();
-  int off = wsum[wave] + v - cnt;
-  for (int p = b; p < e; ++p) {
-    if (state_active(ps[p].status)) {
-      act[off] = p;
-      slot[p] = off++;
-    } else {
-      slot[p] = -1;
-    }
-  }
-  if (t == 0) {
-    RoundTable r;
-    r.nact = total;
-    r.ntiles = (total + kPT - 1) / kPT;
-    r.S = (s_tuned > 0 && r.ntiles == ntiles_full) ? s_tuned : choose_split(r.ntiles, nblocks, n_cu, kSplitMax);
-    r.pad = 0;
-    *rt = r;
-    if (work != nullptr) *work += (unsigned long long)total;
-  }
-}
-
 // Partial reduction for a stand-alone evaluation: F = sum_s Fpart, g = 4 x G.
 __global__ void k_finish_eval(const float* __restrict__ Gpart, const double* __restrict__ Fpart,
                               const float* __restrict__ x, int S, int P, int Pp, int K, int Kp,
@@ -413,13 +355,14 @@ __global__ void k_finish_eval(const float* __restrict__ Gpart, const double* __r
 // stopped by the stop rule or a failed line search: the current point is
 // taken as the iterate again (history kept) and a new direction computed.
 __global__ void k_resume(PlanState* ps, const float* __restrict__ x, float* __restrict__ xt,
-                         int Pp, int Kp, int max_iter, int resume_stopped) {
+                         int* __restrict__ flag, int Pp, int Kp, int max_iter, int resume_stopped) {
   const int p = blockIdx.x;
   if (p >= Pp) return;
   const int s = ps[p].status;
   const bool resume = (s == ST_MAXITER && ps[p].iter < max_iter) ||
                       (resume_stopped && (s == ST_CONVERGED || s == ST_LSFAIL) &&
                        ps[p].iter < max_iter);
+  if (threadIdx.x == 0) flag[p] = (resume || state_active(s)) ? 1 : 0;
   if (!resume) return;
   for (int l = threadIdx.x; l < Kp; l += blockDim.x) xt[(size_t)p * Kp + l] = x[(size_t)p * Kp + l];
   __syncthreads();
@@ -446,14 +389,6 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t st) {
   }
 }
 
-hipError_t launch_compact(const PlanState* ps, int P, int nblocks, int n_cu, int s_tuned,
-                          int ntiles_full, int* act, int* slot, RoundTable* rt,
-                          unsigned long long* work, hipStream_t st) {
-  hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, st, ps, P, nblocks, n_cu, s_tuned,
-                     ntiles_full, act, slot, rt, work);
-  return hipGetLastError();
-}
-
 hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
                            hipStream_t st) {
   if (Kp % 4 != 0) return hipErrorInvalidValue;
@@ -472,9 +407,9 @@ hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const flo
   return hipGetLastError();
 }
 
-hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int Pp, int Kp, int max_iter,
-                         int resume_stopped, hipStream_t st) {
-  hipLaunchKernelGGL(k_resume, dim3(Pp), dim3(128), 0, st, ps, x, xt, Pp, Kp, max_iter,
+hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int* flag, int Pp, int Kp,
+                         int max_iter, int resume_stopped, hipStream_t st) {
+  hipLaunchKernelGGL(k_resume, dim3(Pp), dim3(128), 0, st, ps, x, xt, flag, Pp, Kp, max_iter,
                      resume_stopped);
   return hipGetLastError();
 }
