@@ -128,6 +128,12 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
   return true;
 }
 
+// float4-chunk swizzle of row `row` of the ACC64 kernel's LDS tile
+template <bool ON>
+__device__ inline int swz_row(int row) {
+  return ON ? ((row >> 1) & 3) : 0;
+}
+
 // MODE_F32    : FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4_f32).
 // MODE_ACC64  : FP32 operands, the dose accumulated in FP64
 //               (v_mfma_f64_16x16x4_f64) and the penalty evaluated in FP64.
@@ -140,7 +146,14 @@ enum { MODE_F32 = 0, MODE_ACC64 = 1, MODE_CHUNK64 = 2 };
 template <int KP, int MODE>
 __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   constexpr bool ACC64 = MODE == MODE_ACC64;
-  constexpr int KS = KP + 4;       // LDS row stride (floats): conflict-free both ways
+  // LDS row stride (floats).  The dose product reads rows n = 0..15 as float4
+  // at one column; the back-projection reads 16 consecutive columns of rows
+  // 4q + r (FP32 modes) or q + 4r (ACC64, the FP64 op's row order).  Kp + 4
+  // is conflict-free for the first two patterns; for ACC64 the stride is
+  // Kp + 16 (rows q, q+1 on opposite bank halves) and the float4 chunk index
+  // of row R is XORed with (R >> 1) & 3 so the dose-product reads stay
+  // conflict-free as well.
+  constexpr int KS = ACC64 ? KP + 16 : KP + 4;
   constexpr int NK16 = KP / 16;    // 16-dwell slices
   constexpr int NF4 = 4 * KP;      // float4 per 16-point block
   constexpr int NPF = (NF4 + 255) / 256;
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
       if (NF4 % 256 == 0 || idx < NF4) {                                    \
         const int row = idx / (KP / 4);                                     \
         const int c4 = idx - row * (KP / 4);                                \
-        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * c4]) = pf[i];     \
+        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * (c4 ^ swz_row<ACC64>(row))]) = pf[i]; \
       }                                                                     \
     }                                                                       \
     if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
@@ -244,14 +257,14 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
       d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
-        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
+        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * (q ^ swz_row<ACC64>(n))]);
         acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
         acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
         acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
         acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * k + n], phi_prev[r], gacc[k]);
+          gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * k + (n ^ (swz_row<ACC64>(q + 4 * r) << 2))], phi_prev[r], gacc[k]);
       }
       if (have_cur) {
 #pragma unroll
@@ -259,15 +272,11 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
           const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
           const int gi = sG[cur][q + 4 * r];
           const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-          double kap = 0.0, dev = 0.0;
-          if (d < sP64[gi][1]) {
-            dev = d - sP64[gi][1];
-            kap = sP64[gi][0] * dev;
-          } else if (d > sP64[gi][2]) {
-            dev = d - sP64[gi][2];
-            kap = sP64[gi][3] * dev;
-          }
-          facc += (double)w * (kap * dev);
+          // eq. 1 without branches: at most one of the two deviations is nonzero
+          const double lo = fmin(d - sP64[gi][1], 0.0);
+          const double hi = fmax(d - sP64[gi][2], 0.0);
+          const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
+          facc += (double)w * (kap * (lo + hi));
           phi[r] = (float)((double)w * kap);
         }
       }
@@ -295,15 +304,10 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
           const double d = ds[r];
           const int gi = sG[cur][4 * q + r];
           const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-          double kap = 0.0, dev = 0.0;
-          if (d < sP64[gi][1]) {
-            dev = d - sP64[gi][1];
-            kap = sP64[gi][0] * dev;
-          } else if (d > sP64[gi][2]) {
-            dev = d - sP64[gi][2];
-            kap = sP64[gi][3] * dev;
-          }
-          facc += (double)w * (kap * dev);
+          const double lo = fmin(d - sP64[gi][1], 0.0);
+          const double hi = fmax(d - sP64[gi][2], 0.0);
+          const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
+          facc += (double)w * (kap * (lo + hi));
           phi[r] = (float)((double)w * kap);
         }
       }
@@ -327,15 +331,10 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
           const int gi = sG[cur][4 * q + r];
           const float4 pr = sP[gi];
           const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-          float kap = 0.f, dev = 0.f;
-          if (d < pr.y) {
-            dev = d - pr.y;
-            kap = pr.x * dev;
-          } else if (d > pr.z) {
-            dev = d - pr.z;
-            kap = pr.w * dev;
-          }
-          facc += (double)(w * (kap * dev));
+          const float lo = fminf(d - pr.y, 0.f);
+          const float hi = fmaxf(d - pr.z, 0.f);
+          const float kap = pr.x * lo + pr.w * hi;
+          facc += (double)(w * (kap * (lo + hi)));
           phi[r] = w * kap;
         }
       }
