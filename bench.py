@@ -35,15 +35,17 @@ TOL_V100 = 0.1      # target V100 difference in percentage points
 # workload meets both tolerances (calibrated with --calibrate against the
 # oracle optima in tests/golden/c2_reference_optima.json).
 TIME_EVERY = 16  # rounds between timed rounds in the timed steps
+EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k_eval_f32",
+               "bf16": "k_eval_bf16", "fp8": "k_eval_fp8"}
 
 # HBM bytes per full-batch launch of the FP64-accumulating evaluation kernel on
 # the 360 x 20,000 x 1,000 workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (KiB per dispatch, median of the full-batch dispatches) scaled by the same
 # counters on a 256 MiB copy (read x 2.000, write x 1.000); valid only for the
 # kernel source they were taken on (first 16 hex digits of its SHA-256).
-EVAL_TRAFFIC = {"k_eval_sha256": "b05f096a013c0ed6", "dtype": "f32acc64", "plans": 1000,
-                "fetch_kib": 21305.4, "fetch_scale": 262144.0 / 131092.5,
-                "write_kib": 24747.5, "write_scale": 262144.0 / 262144.0}
+EVAL_TRAFFIC = {"k_eval_sha256": "154b6980ea69c198", "dtype": "f32acc64", "plans": 1000,
+                "fetch_kib": 21270.9, "fetch_scale": 262144.0 / 131091.9,
+                "write_kib": 24708.0, "write_scale": 262144.0 / 262144.0}
 ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
 # MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
 PEAK_F64 = 78.6
@@ -485,7 +487,7 @@ def main(argv=None) -> int:
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_eval_f32 (fused dose product, penalty, back-projection)",
+            "kernel": EVAL_KERNEL.get(stages[-1][0], "k_eval") + " (fused dose product, penalty, back-projection)",
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",

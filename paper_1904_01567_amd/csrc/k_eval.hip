@@ -59,6 +59,7 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
 // the running plans itself (a block-wide scan of the flags), so no separate
 // launch is needed.  Returns false, for the whole workgroup, when the grid
 // is larger than this round's S * ntiles.
+template <int NT>
 __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, float* sW, int& s,
                                   int& S, int& stride, int& j0) {
   const int tid = threadIdx.x;
@@ -73,12 +74,12 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     if (tid < kPT) sPlan[tid] = j0 + tid;
   } else {
     if (tid < kPT) sPlan[tid] = -1;
-    const int per = (a.P + 255) / 256;
+    const int per = (a.P + NT - 1) / NT;
     const int b = tid * per;
     const int e = min(b + per, a.P);
     int cnt = 0;
     for (int p = b; p < e; ++p) cnt += a.flag[p];
-    int v = cnt;  // inclusive scan over the wavefront, then over the 4 waves
+    int v = cnt;  // inclusive scan over the wavefront, then over the waves
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int u = __shfl_up(v, o);
@@ -88,7 +89,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     __syncthreads();
     int base = 0, nact = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       const int t = sScan[w];
       base += w < wave ? t : 0;
       nact += t;
@@ -121,39 +122,30 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     }
   }
   __syncthreads();
-  for (int i = tid; i < kPT * kGmax; i += 256) {
+  for (int i = tid; i < kPT * kGmax; i += NT) {
     const int pl = sPlan[i / kGmax];
     sW[i] = pl >= 0 ? a.wn[(size_t)pl * kGmax + (i % kGmax)] : 0.f;
   }
   return true;
 }
 
-// float4-chunk swizzle of row `row` of the ACC64 kernel's LDS tile
-template <bool ON>
-__device__ inline int swz_row(int row) {
-  return ON ? ((row >> 1) & 3) : 0;
-}
+// float4-chunk swizzle of row `row` of the FP64-accumulating kernel's LDS tile
+__device__ inline int swz_row(int row) { return (row >> 1) & 3; }
 
 // MODE_F32    : FP32 operands, FP32 accumulation (v_mfma_f32_16x16x4_f32).
-// MODE_ACC64  : FP32 operands, the dose accumulated in FP64
-//               (v_mfma_f64_16x16x4_f64) and the penalty evaluated in FP64.
 // MODE_CHUNK64: FP32 matrix ops sum 16 dwells at a time from zero; those
 //               partial doses are accumulated in FP64 on the vector ALU and
 //               the penalty is evaluated in FP64.
-// The back-projection is FP32 in all three.
-enum { MODE_F32 = 0, MODE_ACC64 = 1, MODE_CHUNK64 = 2 };
+// The back-projection is FP32 in both.  (FP32 operands with the dose
+// accumulated in FP64 have a kernel of their own, k_eval_acc64, below.)
+enum { MODE_F32 = 0, MODE_CHUNK64 = 2 };
 
 template <int KP, int MODE>
 __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
-  constexpr bool ACC64 = MODE == MODE_ACC64;
-  // LDS row stride (floats).  The dose product reads rows n = 0..15 as float4
-  // at one column; the back-projection reads 16 consecutive columns of rows
-  // 4q + r (FP32 modes) or q + 4r (ACC64, the FP64 op's row order).  Kp + 4
-  // is conflict-free for the first two patterns; for ACC64 the stride is
-  // Kp + 16 (rows q, q+1 on opposite bank halves) and the float4 chunk index
-  // of row R is XORed with (R >> 1) & 3 so the dose-product reads stay
-  // conflict-free as well.
-  constexpr int KS = ACC64 ? KP + 16 : KP + 4;
+  // LDS row stride (floats): the dose product reads rows n = 0..15 as float4
+  // at one column, the back-projection 16 consecutive columns of rows
+  // 4q + r; Kp + 4 is conflict-free for both.
+  constexpr int KS = KP + 4;
   constexpr int NK16 = KP / 16;    // 16-dwell slices
   constexpr int NF4 = 4 * KP;      // float4 per 16-point block
   constexpr int NPF = (NF4 + 255) / 256;
@@ -173,7 +165,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   const int n = lane & 15;
 
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -227,7 +219,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
       if (NF4 % 256 == 0 || idx < NF4) {                                    \
         const int row = idx / (KP / 4);                                     \
         const int c4 = idx - row * (KP / 4);                                \
-        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * (c4 ^ swz_row<ACC64>(row))]) = pf[i]; \
+        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * c4]) = pf[i];     \
       }                                                                     \
     }                                                                       \
     if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
@@ -252,35 +244,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
     float phi[4] = {0.f, 0.f, 0.f, 0.f};
     const float* __restrict__ Dc = sD[cur];
     const float* __restrict__ Dp = sD[prv];
-    if constexpr (ACC64) {
-      // four independent accumulation chains keep the FP64 pipe busy
-      d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
-#pragma unroll
-      for (int k = 0; k < NK16; ++k) {
-        const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * (q ^ swz_row<ACC64>(n))]);
-        acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
-        acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
-        acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
-        acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * k + (n ^ (swz_row<ACC64>(q + 4 * r) << 2))], phi_prev[r], gacc[k]);
-      }
-      if (have_cur) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double d = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
-          const int gi = sG[cur][q + 4 * r];
-          const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-          // eq. 1 without branches: at most one of the two deviations is nonzero
-          const double lo = fmin(d - sP64[gi][1], 0.0);
-          const double hi = fmax(d - sP64[gi][2], 0.0);
-          const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
-          facc += (double)w * (kap * (lo + hi));
-          phi[r] = (float)((double)w * kap);
-        }
-      }
-    } else if constexpr (MODE == MODE_CHUNK64) {
+    if constexpr (MODE == MODE_CHUNK64) {
       const f4v z = {0.f, 0.f, 0.f, 0.f};
       double ds[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -358,6 +322,176 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// MODE_ACC64 (FP32 operands, FP64-accumulated dose, FP64 penalty, FP32
+// back-projection) with 512 threads: two waves per SIMD.  The FP64 matrix op
+// reaches its full rate only when two waves per SIMD issue it, and a wave
+// that holds t and the gradient accumulators of 16 plans over all Kp dwells
+// does not fit in half the register file.  So the 8 waves form 4 plan groups
+// (16 plans each) x 2 dwell halves: each wave forms the partial dose of its
+// dwell half, the two partials of a plan group are added through LDS in a
+// fixed order, both waves evaluate eq. 1 on the sum, and each back-projects
+// onto its own dwell half.  Same software pipeline as the 256-thread kernel
+// (dose product of block b with the back-projection of block b-1, two LDS
+// buffers), with two barriers per block.
+// LDS tile row stride Kp + 16 with the float4 chunk index of row R XORed with
+// (R >> 1) & 3: the back-projection reads 16 columns of rows q + 4r (the FP64
+// op's row order), which that stride puts on opposite bank halves for
+// q = 0, 1, and the swizzle keeps the dose product's float4 reads of rows
+// 0..15 conflict-free.
+// ---------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
+  constexpr int NT = 512;
+  constexpr int KS = KP + 16;
+  constexpr int NKH = KP / 32;      // 16-dwell slices per dwell half
+  constexpr int NF4 = 4 * KP;       // float4 per 16-point block
+  constexpr int NPF = (NF4 + NT - 1) / NT;
+
+  __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
+  __shared__ double sX[2][4][4][64];  // partial doses [half][group][r][lane]
+  __shared__ float sW[kPT * kGmax];
+  __shared__ int sPlan[kPT];
+  __shared__ int sScan[NT / 64];
+  __shared__ double sP64[kGmax + 1][4];
+  __shared__ int sG[2][kBM];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  const int grp = wave & 3;   // plan group: columns 16 grp .. 16 grp + 15
+  const int half = wave >> 2; // dwell half: slices half * NKH .. half * NKH + NKH - 1
+
+  int s, S, stride, j0;
+  if (!tile_setup<NT>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+#pragma unroll
+  for (int j = 0; j <= kGmax; ++j)
+    if (tid == j) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sP64[j][c] = a.gt.prm64[j][c];
+    }
+
+  const int col = grp * 16 + n;
+  const int plan = sPlan[col];
+  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP + half * (KP / 2);
+  // t = x^2 of plan n at dwells 16 k + 4 q + j of this wave's half (slice k)
+  float tf[KP / 8];
+#pragma unroll
+  for (int k = 0; k < NKH; ++k) {
+    const float4 xv = *reinterpret_cast<const float4*>(xrow + 16 * k + 4 * q);
+    tf[4 * k + 0] = pv ? xv.x * xv.x : 0.f;
+    tf[4 * k + 1] = pv ? xv.y * xv.y : 0.f;
+    tf[4 * k + 2] = pv ? xv.z * xv.z : 0.f;
+    tf[4 * k + 3] = pv ? xv.w * xv.w : 0.f;
+  }
+  f4v gacc[NKH];
+#pragma unroll
+  for (int k = 0; k < NKH; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
+  double facc = 0.0;
+
+  const int b_begin = (int)(((long long)s * a.nblocks) / S);
+  const int b_end = (int)(((long long)(s + 1) * a.nblocks) / S);
+  const f4v* __restrict__ Dg = reinterpret_cast<const f4v*>(a.D);
+
+  f4v pf[NPF];
+  int gpre = 0;
+#define GMCO_PF64(blk)                                                      \
+  {                                                                         \
+    const f4v* src_ = Dg + (size_t)(blk) * NF4;                             \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
+      const int idx = tid + NT * i;                                         \
+      if (NF4 % NT == 0 || idx < NF4) pf[i] = src_[idx];                    \
+    }                                                                       \
+    if (tid < kBM) gpre = a.grp[(blk) * kBM + tid];                         \
+  }
+#define GMCO_ST64(buf)                                                      \
+  {                                                                         \
+    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
+      const int idx = tid + NT * i;                                         \
+      if (NF4 % NT == 0 || idx < NF4) {                                     \
+        const int row = idx / (KP / 4);                                     \
+        const int c4 = idx - row * (KP / 4);                                \
+        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * (c4 ^ swz_row(row))]) = pf[i]; \
+      }                                                                     \
+    }                                                                       \
+    if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
+  }
+
+  float phi_prev[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int i = tid; i < kBM * KS; i += NT) sD[1][i] = 0.f;
+  if (b_begin < b_end) GMCO_PF64(b_begin);
+#pragma unroll 1
+  for (int b = b_begin; b <= b_end; ++b) {
+    const int cur = (b - b_begin) & 1;
+    const int prv = cur ^ 1;
+    // As in the 256-thread kernel: the first iteration back-projects
+    // phi_prev = 0 over a zeroed buffer and the last repeats a dose product
+    // whose result is discarded.
+    const bool have_cur = b < b_end;
+    // Buffer `cur` was last read by the previous iteration's matrix loop,
+    // which every wave finished before that iteration's second barrier.
+    if (have_cur) GMCO_ST64(cur);
+    __syncthreads();
+    if (b + 1 < b_end) GMCO_PF64(b + 1);
+
+    const float* __restrict__ Dc = sD[cur];
+    const float* __restrict__ Dp = sD[prv];
+    d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+#pragma unroll
+    for (int k = 0; k < NKH; ++k) {
+      const int kg = half * NKH + k;
+      const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * kg + 4 * (q ^ swz_row(n))]);
+      acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
+      acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
+      acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
+      acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * kg + (n ^ (swz_row(q + 4 * r) << 2))],
+                           phi_prev[r], gacc[k]);
+    }
+    // partial dose of points q + 4 r (the FP64 op's rows) for plan n
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sX[half][grp][r][lane] = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
+    __syncthreads();
+    float phi[4] = {0.f, 0.f, 0.f, 0.f};
+    if (have_cur) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double d = sX[0][grp][r][lane] + sX[1][grp][r][lane];
+        const int gi = sG[cur][q + 4 * r];
+        const float w = (gi < kGmax) ? sW[col * kGmax + gi] : 0.f;
+        // eq. 1 without branches: at most one of the two deviations is nonzero
+        const double lo = fmin(d - sP64[gi][1], 0.0);
+        const double hi = fmax(d - sP64[gi][2], 0.0);
+        const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
+        facc += (double)w * (kap * (lo + hi));
+        phi[r] = (float)((double)w * kap);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) phi_prev[r] = phi[r];
+  }
+#undef GMCO_PF64
+#undef GMCO_ST64
+
+  // ---- split partials: each wave its dwell half; F from one wave per group ----
+  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP + half * (KP / 2);
+#pragma unroll
+  for (int k = 0; k < NKH; ++k) {
+    *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
+        make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  }
+  if (half == 0) {
+    facc += __shfl_xor(facc, 16);
+    facc += __shfl_xor(facc, 32);
+    if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16.  Lane l
 // (q = l / 16, n = l % 16) supplies A[n][8q .. 8q+7] and B[8q .. 8q+7][n];
 // accumulator register r holds C[4q + r][n].  Blocks of 32 points: the dose
@@ -400,7 +534,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
   const int q = lane >> 4;
   const int n = lane & 15;
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];
@@ -569,7 +703,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   const int q = lane >> 4;
   const int n = lane & 15;
   int s, S, stride, j0;
-  if (!tile_setup(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) sP[j] = a.gt.prm[j];
@@ -716,7 +850,7 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   if (a.grid < 1) return hipErrorInvalidValue;
   const dim3 grid(a.grid), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_f32<KP, MODE_ACC64>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_eval_acc64<KP>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
