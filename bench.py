@@ -173,6 +173,50 @@ def eps_sweep(args) -> int:
     return 0
 
 
+def surface_volume(args) -> int:
+    """The 8-group objective (surface and volume rows of Table 1, one hidden
+    weight per organ) on the paper-scale layout, with the DVH metrics on a
+    separate 5x denser point set: optimisation time and metrics time."""
+    import numpy as np
+    import torch
+
+    import cases
+    from paper_1904_01567_amd import Planner, class_solution
+    case = cases.case_sv_c2()
+    W = cases.weights_c2(args.plans)
+    iters = args.iters or ITERS.get(args.dtype, 2000)
+    pl = Planner(dtype=args.dtype, max_plans=args.plans)
+    t0 = time.perf_counter()
+    pl.load(case, class_solution.SURFACE_VOLUME)
+    torch.cuda.synchronize()
+    t_load = time.perf_counter() - t0
+    for k in range(args.warmup + args.steps):
+        pl.set_weights(W)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = pl.optimize(max_iter=iters, eps=args.eps)
+        torch.cuda.synchronize()
+        t_opt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        m = pl.metrics()
+        best, cls, nd, frac = pl.select_plan()
+        torch.cuda.synchronize()
+        t_met = time.perf_counter() - t0
+    print(json.dumps({
+        "workload": f"{case.K} dwells, {case.M} optimisation points in 8 groups (surface and volume "
+                    f"of 4 organs), {case.dvh_xyz.shape[0]} DVH points, {args.plans} plans, "
+                    f"{iters} iterations, eps {args.eps}",
+        "dtype": DTYPE_NAMES[args.dtype], "plans_per_s": args.plans / t_opt, "optimize_s": t_opt,
+        "metrics_and_selection_s": t_met, "load_case_s": t_load, "rounds": info["rounds"],
+        "workspace_GB": pl.workspace_bytes(case.M, case.K, case.dvh_xyz.shape[0]) / 1e9,
+        "status_counts": {k: int(np.sum(m["status"] == v)) for k, v in
+                          (("converged", 1), ("maxiter", 2), ("ls_fail", 3))},
+        "median_V100_target_pct": float(np.median(m["V100_pct"][:, 0])),
+        "rtog_plus": int(np.sum(cls == 2)), "rtog": int(np.sum(cls == 1)),
+        "nondominated_fraction": frac, "selected": best}), flush=True)
+    return 0
+
+
 def plan_sweep(args) -> int:
     """Time and device memory against the number of plans (Fig. 4 of the
     paper): one context per batch size, same case, same iteration cap."""
@@ -190,13 +234,14 @@ def plan_sweep(args) -> int:
         pl.set_weights(W)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = pl.optimize(max_iter=iters)
+        info = pl.optimize(max_iter=iters, eps=args.eps)
         pl.metrics()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         print(json.dumps({"plans": P, "seconds": dt, "ms_per_plan": 1e3 * dt / P,
                           "plans_per_s": P / dt, "rounds": info["rounds"],
-                          "workspace_GB": ws / 1e9, "iterations": iters}), flush=True)
+                          "workspace_GB": ws / 1e9, "max_iterations": iters, "eps": args.eps,
+                          "max_iters_taken": info["max_iters"]}), flush=True)
         pl.close()
         torch.cuda.empty_cache()
     return 0
@@ -329,7 +374,7 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32chunk64", "f32", "bf16"])
+    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32chunk64", "f32", "bf16", "fp8"])
     ap.add_argument("--ladder", type=str, default=None,
                     help="precision ladder, e.g. bf16:150,f32acc64:2000 (iteration caps are "
                          "cumulative); the context is created with the first dtype")
@@ -348,8 +393,12 @@ def main(argv=None) -> int:
     ap.add_argument("--eps-sweep", type=str, default=None,
                     help="comma-separated stop thresholds: time, iterations and non-dominated "
                          "fraction at each (speed-up relative to the first)")
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="stop threshold of --plan-sweep (0: every plan runs --iters steps)")
     ap.add_argument("--plan-sweep", type=str, default=None,
                     help="comma-separated batch sizes: time and device memory at each")
+    ap.add_argument("--surface-volume", action="store_true",
+                    help="8-group objective with a separate DVH point set (paper-scale layout)")
     ap.add_argument("--precision-report", action="store_true",
                     help="per arithmetic: objective, target V100 and OAR D10 errors of the "
                          "sampled plans against the FP64 oracle optima")
@@ -389,6 +438,8 @@ def main(argv=None) -> int:
         return eps_sweep(args)
     if args.plan_sweep:
         return plan_sweep(args)
+    if args.surface_volume:
+        return surface_volume(args)
     stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
     if args.ladder:
         stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]

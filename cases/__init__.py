@@ -53,6 +53,10 @@ class Case:
     semi_axes: tuple = (2.0, 1.75, 1.75)
     prescription_gy: float = PRESCRIPTION_GY
     meta: dict = field(default_factory=dict)
+    # surface / volume variant: group -> organ map and a separate DVH point set
+    group_organ: np.ndarray = None  # (G,) int32, None: every group is an organ
+    dvh_xyz: np.ndarray = None      # (M_dvh, 3) float64, cm
+    dvh_organ: np.ndarray = None    # (M_dvh,) int32
 
     @property
     def K(self) -> int:
@@ -162,6 +166,98 @@ def make_case(n_cath: int, n_dwell: int, n_points, seed: int,
                 semi_axes=tuple(float(v) for v in a),
                 meta=dict(n_cath=n_cath, n_dwell=n_dwell, seed=seed,
                           jitter=jitter))
+
+
+# ---------------------------------------------------------------------------
+# Surface and volume points (Table 1 lists both for every organ): 8 groups,
+# group 2 j + 0 the surface and 2 j + 1 the volume points of organ j, and a
+# separate, denser DVH point set labelled by organ (Sec. 2.1.1 counts about
+# five DVH points per optimisation point).
+#   target surface: points on the ellipsoid (scaled unit directions);
+#   urethra surface: the 0.3 cm cylinder; urethra volume: inside it;
+#   bladder / rectum surface: the two faces of the slab over its footprint.
+# ---------------------------------------------------------------------------
+SV_GROUP_ORGAN = np.array([0, 0, 1, 1, 2, 2, 3, 3], dtype=np.int32)
+
+
+def _ellipsoid_surface(rng, n, a):
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    return u * np.asarray(a)
+
+
+def _urethra_volume(rng, n, a):
+    ang = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    r = URETHRA_RADIUS_CM * np.sqrt(rng.uniform(0.0, 1.0, size=n))
+    z = rng.uniform(-a[2], a[2], size=n)
+    return np.stack([r * np.cos(ang), r * np.sin(ang), z], axis=1)
+
+
+def _slab_faces(rng, n, a, y_lo, y_hi):
+    pts = _slab(rng, n, a, y_lo, y_hi)
+    pts[:, 1] = np.where(rng.uniform(size=n) < 0.5, y_lo, y_hi)
+    return pts
+
+
+def _organ_samplers(a):
+    yb = (a[1] + SLAB_NEAR_CM, a[1] + SLAB_FAR_CM)
+    yr = (-a[1] - SLAB_FAR_CM, -a[1] - SLAB_NEAR_CM)
+    surface = [lambda r, n: _ellipsoid_surface(r, n, a), lambda r, n: _urethra(r, n, a),
+               lambda r, n: _slab_faces(r, n, a, *yb), lambda r, n: _slab_faces(r, n, a, *yr)]
+    volume = [lambda r, n: _uniform_ellipsoid(r, n, a), lambda r, n: _urethra_volume(r, n, a),
+              lambda r, n: _slab(r, n, a, *yb), lambda r, n: _slab(r, n, a, *yr)]
+    return surface, volume
+
+
+def make_case_sv(n_cath: int, n_dwell: int, n_points, seed: int, dvh_points=None,
+                 semi_axes=(2.0, 1.75, 1.75), jitter: float = 0.0) -> Case:
+    """Seeded case with surface and volume points.  n_points = 8 counts in
+    group order (target surface, target volume, urethra surface, ...);
+    dvh_points = 4 per-organ counts of the DVH set (None: no DVH set)."""
+    rng = np.random.default_rng(seed)
+    a = np.asarray(semi_axes, dtype=np.float64)
+    z_scale = 1.0
+    if jitter > 0.0:
+        f = rng.uniform(1.0 - jitter, 1.0 + jitter, size=3)
+        a = a * f
+        z_scale = f[2]
+    surface, volume = _organ_samplers(a)
+    counts = [int(v) for v in n_points]
+    pts, group = [], []
+    for g, n in enumerate(counts):
+        j, kind = divmod(g, 2)
+        pts.append((surface if kind == 0 else volume)[j](rng, n))
+        group.append(np.full(n, g, dtype=np.int32))
+    c = Case(dwell_xyz=dwell_positions(n_cath, n_dwell, z_scale),
+             pt_xyz=np.ascontiguousarray(np.concatenate(pts, axis=0)),
+             group=np.concatenate(group), volume_cc=structure_volumes(a),
+             semi_axes=tuple(float(v) for v in a),
+             meta=dict(n_cath=n_cath, n_dwell=n_dwell, seed=seed, jitter=jitter, surface_volume=True),
+             group_organ=SV_GROUP_ORGAN.copy())
+    if dvh_points is not None:
+        drng = np.random.default_rng(seed + 100_000)
+        dp, dl = [], []
+        for j, n in enumerate(int(v) for v in dvh_points):
+            dp.append(volume[j](drng, n))
+            dl.append(np.full(n, j, dtype=np.int32))
+        c.dvh_xyz = np.ascontiguousarray(np.concatenate(dp, axis=0))
+        c.dvh_organ = np.concatenate(dl)
+    return c
+
+
+def case_sv_small() -> Case:
+    """8-group case for parity tests: 12 x 8 dwells, 1,300 optimisation points,
+    a DVH set of 3,250."""
+    return make_case_sv(12, 8, (150, 500, 100, 100, 75, 150, 75, 150), seed=31,
+                        dvh_points=(1300, 500, 725, 725))
+
+
+def case_sv_c2() -> Case:
+    """The 360-dwell paper-scale layout with surface and volume points
+    (20,000: target 2,000 + 8,000, urethra 1,000 + 1,000, bladder and rectum
+    1,000 + 3,000 each) and a 5x denser DVH set (100,000 points)."""
+    return make_case_sv(18, 20, (2000, 8000, 1000, 1000, 1000, 3000, 1000, 3000), seed=2,
+                        dvh_points=(50000, 10000, 20000, 20000))
 
 
 def hidden_weights(n_plans: int, seed: int, n_struct: int = 4,

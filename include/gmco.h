@@ -82,8 +82,14 @@ typedef struct {
 } gmco_opts;
 
 /* One patient case (Sec. 2.1).  Points may be given in any order; group[i]
- * names the structure of point i.  Table 1 gives the class-solution
- * parameters for the four prostate structures. */
+ * names the row of eq. 1 parameters of point i.  Groups belong to organs
+ * (structures): eq. (obj) gives each organ one hidden weight w_j and one
+ * point count N_pnt,j, shared by its groups, e.g. the surface and the volume
+ * points of Table 1 (8 groups, 4 organs).  Without group_organ every group is
+ * an organ of its own.  Metrics (V100, V75, D10, D90, individual objectives)
+ * are per organ.  The DVH metrics use the optional DVH point set when given
+ * (Sec. 2.1.1 counts separate, denser DVH points), else the optimisation
+ * points; F and the individual objectives always use the optimisation points. */
 typedef struct {
   int n_dwells;                  /* K, 1..GMCO_MAX_DWELLS */
   const double* dwell_xyz;       /* K x 3, cm */
@@ -92,12 +98,20 @@ typedef struct {
   const int32_t* group;          /* M, values in [0, n_groups) */
   int n_groups;                  /* 1..GMCO_MAX_GROUPS */
   const double* group_params;    /* n_groups x 4: w_min, D_min [Gy], D_max [Gy], w_max (eq. 1) */
-  const double* group_volume_cc; /* n_groups structure volumes for V75 in cc; NULL -> 0 cc */
+  const double* group_volume_cc; /* n_organs structure volumes for V75 in cc; NULL -> 0 cc */
   double prescription_gy;        /* > 0; 100 % for V100 / D_x */
-  int target_group;              /* structure whose mean dose sets the default start */
+  int target_group;              /* organ whose mean dose sets the default start */
   const double* dose_rate;       /* optional M x K dose-rate matrix (Gy per time unit);
                                     NULL -> the point-source law
                                     (1 - 0.01 r) / max(r, 0.1 cm)^2, Sec. 2.2.1 step (i) */
+  const int32_t* group_organ;    /* optional n_groups: organ of each group, in [0, n_organs);
+                                    NULL -> organ j = group j */
+  int n_organs;                  /* organs when group_organ != NULL (1..n_groups); the
+                                    hidden weights of gmco_set_weights are per organ */
+  int n_dvh_points;              /* optional DVH point set (0: none); needs point_xyz-style
+                                    positions and the point-source law */
+  const double* dvh_xyz;         /* n_dvh_points x 3, cm */
+  const int32_t* dvh_organ;      /* n_dvh_points, organ of each DVH point */
 } gmco_case;
 
 /* Options of one optimisation run.  The paper leaves its L-BFGS details out
@@ -167,9 +181,10 @@ int gmco_destroy(gmco_ctx* ctx);
  * stream).  The library does not own the stream. */
 int gmco_set_stream(gmco_ctx* ctx, void* stream);
 
-/* Device bytes needed for a case of M points and K dwells with the context's
- * max_plans, history and dtype. */
-int gmco_workspace_bytes(const gmco_ctx* ctx, int n_points, int n_dwells, size_t* bytes);
+/* Device bytes needed for a case of M points, K dwells and n_dvh_points DVH
+ * points (0: none) with the context's max_plans, history and dtype. */
+int gmco_workspace_bytes(const gmco_ctx* ctx, int n_points, int n_dwells, int n_dvh_points,
+                         size_t* bytes);
 
 /* Hand the library a device buffer (256-byte aligned) to carve all its device
  * arrays from, instead of allocating its own.  The caller keeps ownership and
@@ -185,7 +200,8 @@ int gmco_bind_workspace(gmco_ctx* ctx, void* device_ptr, size_t bytes);
  * Errors: EINVAL, ENOMEM, EHIP. */
 int gmco_load_case(gmco_ctx* ctx, const gmco_case* c);
 
-/* Set the hidden-weight batch, eq. (obj): W is P x n_groups, finite and >= 0,
+/* Set the hidden-weight batch, eq. (obj): W is P x n_organs (n_groups without
+ * group_organ), finite and >= 0,
  * used as given (normalise rows to sum 1 beforehand for the paper's weighted
  * sum).  t0 is P x K start dwell times (> 0 recommended: x_l = 0 is a fixed
  * point of the x^2 substitution) or NULL for the uniform start t_bar.  Resets

@@ -40,6 +40,11 @@ CLASS_SOLUTION_VOLUME = np.array([
     [0.0, 0.0, 7.5, 15.0],
 ])
 
+# Surface and volume rows interleaved: group 2 j + 0 is the surface and
+# 2 j + 1 the volume of structure j.
+CLASS_SOLUTION_SV = np.array([CLASS_SOLUTION_SURFACE[j // 2] if j % 2 == 0 else
+                              CLASS_SOLUTION_VOLUME[j // 2] for j in range(8)])
+
 # Per-plan status codes (shared meaning with the library, defined separately).
 RUNNING, CONVERGED, MAXITER, LS_FAIL, NONFINITE = 0, 1, 2, 3, 4
 
@@ -108,51 +113,62 @@ def group_sizes(group: np.ndarray, n_groups: int) -> np.ndarray:
     return np.bincount(group, minlength=n_groups).astype(np.float64)
 
 
-def point_weights(W: np.ndarray, group: np.ndarray, n_groups: int) -> np.ndarray:
-    """(P, M) factor w_j / N_pnt,j of eq. (obj) for each plan and point.
-    A structure with no points contributes nothing."""
-    N = group_sizes(group, n_groups)
+def point_organs(group: np.ndarray, group_organ=None) -> np.ndarray:
+    """(M,) organ of each point.  Without a map every group is an organ; with
+    one, the surface and volume groups of Table 1 belong to one organ, whose
+    hidden weight w_j and point count N_pnt,j eq. (obj) uses for both."""
+    return group if group_organ is None else np.asarray(group_organ)[group]
+
+
+def point_weights(W: np.ndarray, group: np.ndarray, n_groups: int, group_organ=None) -> np.ndarray:
+    """(P, M) factor w_j / N_pnt,j of eq. (obj) for each plan and point, j the
+    point's organ.  An organ with no points contributes nothing."""
+    W = np.asarray(W, dtype=np.float64)
+    organ = point_organs(group, group_organ)
+    N = group_sizes(organ, n_groups if group_organ is None else W.shape[1])
     inv = np.where(N > 0, 1.0 / np.where(N > 0, N, 1.0), 0.0)
-    return (np.asarray(W, dtype=np.float64) * inv[None, :])[:, group]
+    return (W * inv[None, :])[:, organ]
 
 
 # ---------------------------------------------------------------------------
 # Eq. (obj): F = sum_j w_j (1/N_j) sum_i f_ij.
 # ---------------------------------------------------------------------------
-def organ_objectives(D, t, group, params):
-    """(P, G) individual objectives (1/N_j) sum_{i in j} f_ij."""
+def organ_objectives(D, t, group, params, group_organ=None):
+    """(P, O) individual objectives (1/N_j) sum_{i in j} f_ij per organ j, each
+    point's penalty with its own group's parameters."""
     t = np.atleast_2d(t)
-    G = params.shape[0]
+    organ = point_organs(group, group_organ)
+    O = params.shape[0] if group_organ is None else int(np.max(group_organ)) + 1
     f = penalty(dose(D, t), *point_params(group, params))
-    N = group_sizes(group, G)
-    out = np.zeros((t.shape[0], G))
-    for j in range(G):
+    N = group_sizes(organ, O)
+    out = np.zeros((t.shape[0], O))
+    for j in range(O):
         if N[j] > 0:
-            out[:, j] = f[:, group == j].sum(axis=1) / N[j]
+            out[:, j] = f[:, organ == j].sum(axis=1) / N[j]
     return out
 
 
-def objective(D, t, group, params, W):
+def objective(D, t, group, params, W, group_organ=None):
     """(P,) weighted-sum objective F of eq. (obj) at dwell times t."""
     t = np.atleast_2d(t)
     f = penalty(dose(D, t), *point_params(group, params))
-    return (point_weights(W, group, params.shape[0]) * f).sum(axis=1)
+    return (point_weights(W, group, params.shape[0], group_organ) * f).sum(axis=1)
 
 
-def gradient_x(D, x, group, params, W):
+def gradient_x(D, x, group, params, W, group_organ=None):
     """(P, K) gradient of F with respect to the dwell weights x: eq. 2,
     4 Ddot_il x_l w (d_i - D_bound), weighted by w_j / N_j and summed."""
     x = np.atleast_2d(x)
     d = dose(D, dwell_times(x))
     kappa = penalty_kappa(d, *point_params(group, params))
-    c = point_weights(W, group, params.shape[0]) * kappa
+    c = point_weights(W, group, params.shape[0], group_organ) * kappa
     return 4.0 * x * (c @ D)
 
 
-def objective_and_gradient_x(D, x, group, params, W):
+def objective_and_gradient_x(D, x, group, params, W, group_organ=None):
     x = np.atleast_2d(x)
-    return (objective(D, dwell_times(x), group, params, W),
-            gradient_x(D, x, group, params, W))
+    return (objective(D, dwell_times(x), group, params, W, group_organ),
+            gradient_x(D, x, group, params, W, group_organ))
 
 
 # ---------------------------------------------------------------------------
@@ -289,7 +305,7 @@ def lbfgs_plan(x0, opts: LbfgsOptions, record: bool = False):
     return res
 
 
-def optimize(D, group, params, W, x0, opts: LbfgsOptions, record=False):
+def optimize(D, group, params, W, x0, opts: LbfgsOptions, record=False, group_organ=None):
     """Run one L-BFGS per plan.  Plans are independent; each round evaluates
     every plan that is waiting for a point with one batched dose product."""
     W = np.atleast_2d(np.asarray(W, dtype=np.float64))
@@ -302,7 +318,7 @@ def optimize(D, group, params, W, x0, opts: LbfgsOptions, record=False):
     while pending:
         idx = sorted(pending)
         X = np.stack([pending[p] for p in idx])
-        F, G = objective_and_gradient_x(D, X, group, params, W[idx])
+        F, G = objective_and_gradient_x(D, X, group, params, W[idx], group_organ)
         rounds += 1
         nxt = {}
         for j, p in enumerate(idx):
@@ -341,21 +357,28 @@ def d_percent(d, x_pct: int, prescription_gy):
     return 100.0 * d[k - 1] / prescription_gy
 
 
-def plan_metrics(D, t, group, params, W, volume_cc, prescription_gy):
-    """Per plan: F (FP64), individual objectives, target V100 %, D10 / D90 %
-    and V75 cc per structure."""
+def plan_metrics(D, t, group, params, W, volume_cc, prescription_gy, group_organ=None,
+                 D_dvh=None, dvh_organ=None):
+    """Per plan: F (FP64), individual objectives, V100 %, D10 / D90 % and
+    V75 cc per organ.  F and the individual objectives use the optimisation
+    points; the DVH metrics use the separate DVH point set when one is given
+    (D_dvh with organ labels dvh_organ), else the optimisation points."""
     t = np.atleast_2d(t)
-    G = params.shape[0]
-    d = dose(D, t)
-    F = objective(D, t, group, params, W)
-    fo = organ_objectives(D, t, group, params)
+    organ = point_organs(group, group_organ)
+    G = params.shape[0] if group_organ is None else int(np.max(group_organ)) + 1
+    if D_dvh is None:
+        d, lab = dose(D, t), organ
+    else:
+        d, lab = dose(D_dvh, t), np.asarray(dvh_organ)
+    F = objective(D, t, group, params, W, group_organ)
+    fo = organ_objectives(D, t, group, params, group_organ)
     out = []
     for p in range(t.shape[0]):
         m = dict(F=float(F[p]), f_organ=fo[p].copy(),
                  V100_pct=np.zeros(G), V75_cc=np.zeros(G),
                  D10_pct=np.zeros(G), D90_pct=np.zeros(G))
         for j in range(G):
-            dj = d[p, group == j]
+            dj = d[p, lab == j]
             m["V100_pct"][j] = 100.0 * v_fraction(dj, 100, prescription_gy)
             m["V75_cc"][j] = volume_cc[j] * v_fraction(dj, 75, prescription_gy)
             m["D10_pct"][j] = d_percent(dj, 10, prescription_gy)

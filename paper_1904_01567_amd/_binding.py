@@ -53,7 +53,10 @@ class gmco_case(C.Structure):
                 ("group_params", C.POINTER(C.c_double)),
                 ("group_volume_cc", C.POINTER(C.c_double)),
                 ("prescription_gy", C.c_double), ("target_group", C.c_int),
-                ("dose_rate", C.POINTER(C.c_double))]
+                ("dose_rate", C.POINTER(C.c_double)),
+                ("group_organ", C.POINTER(C.c_int32)), ("n_organs", C.c_int),
+                ("n_dvh_points", C.c_int), ("dvh_xyz", C.POINTER(C.c_double)),
+                ("dvh_organ", C.POINTER(C.c_int32))]
 
 
 class gmco_run(C.Structure):
@@ -105,7 +108,7 @@ def load_library(path: Optional[str] = None):
     lib.gmco_create.argtypes = [C.POINTER(vp), C.POINTER(gmco_opts)]
     lib.gmco_destroy.argtypes = [vp]
     lib.gmco_set_stream.argtypes = [vp, vp]
-    lib.gmco_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    lib.gmco_workspace_bytes.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     lib.gmco_bind_workspace.argtypes = [vp, vp, C.c_size_t]
     lib.gmco_load_case.argtypes = [vp, C.POINTER(gmco_case)]
     lib.gmco_set_weights.argtypes = [vp, C.c_int, dp, dp]
@@ -173,7 +176,7 @@ class Planner:
         opts = gmco_opts(device, DTYPES[dtype], history, max_plans)
         self._check(self.lib.gmco_create(C.byref(self._ctx), C.byref(opts)), "create")
         self.dtype, self.history, self.max_plans, self.device = dtype, history, max_plans, device
-        self.K = self.M = self.G = 0
+        self.K = self.M = self.G = self.O = 0
         self.P = 0
         if use_torch:
             import torch  # device memory and stream come from PyTorch
@@ -213,15 +216,19 @@ class Planner:
     def set_stream(self, stream_handle: int):
         self._check(self.lib.gmco_set_stream(self._ctx, C.c_void_p(stream_handle)), "set_stream")
 
-    def workspace_bytes(self, n_points: int, n_dwells: int) -> int:
+    def workspace_bytes(self, n_points: int, n_dwells: int, n_dvh_points: int = 0) -> int:
         b = C.c_size_t()
-        self._check(self.lib.gmco_workspace_bytes(self._ctx, n_points, n_dwells, C.byref(b)),
-                    "workspace_bytes")
+        self._check(self.lib.gmco_workspace_bytes(self._ctx, n_points, n_dwells, n_dvh_points,
+                                                  C.byref(b)), "workspace_bytes")
         return int(b.value)
 
     # -- API -------------------------------------------------------------
     def load_case(self, dwell_xyz, point_xyz, group, group_params, volume_cc=None,
-                  prescription_gy: float = 15.0, target_group: int = 0, dose_rate=None):
+                  prescription_gy: float = 15.0, target_group: int = 0, dose_rate=None,
+                  group_organ=None, dvh_xyz=None, dvh_organ=None):
+        """group_organ (n_groups,) maps parameter groups to organs (hidden
+        weights, point counts, metrics); dvh_xyz / dvh_organ give a separate
+        point set for the DVH metrics."""
         dw = _f64(dwell_xyz)
         K = dw.shape[0]
         grp = np.ascontiguousarray(np.asarray(group, dtype=np.int32))
@@ -229,31 +236,49 @@ class Planner:
         pts = _f64(point_xyz, (M, 3)) if point_xyz is not None else None
         prm = _f64(group_params)
         G = prm.shape[0]
-        vol = _f64(volume_cc, (G,)) if volume_cc is not None else None
+        gorg = None
+        O = G
+        if group_organ is not None:
+            gorg = np.ascontiguousarray(np.asarray(group_organ, dtype=np.int32))
+            if gorg.shape != (G,):
+                raise ValueError(f"group_organ must have {G} entries")
+            O = int(gorg.max()) + 1
+        vol = _f64(volume_cc, (O,)) if volume_cc is not None else None
         Dr = _f64(dose_rate, (M, K)) if dose_rate is not None else None
+        Md = 0
+        dxyz = dorg = None
+        if dvh_xyz is not None:
+            dorg = np.ascontiguousarray(np.asarray(dvh_organ, dtype=np.int32))
+            Md = dorg.shape[0]
+            dxyz = _f64(dvh_xyz, (Md, 3))
         if self._torch is not None:
-            nbytes = self.workspace_bytes(M, K)
+            nbytes = self.workspace_bytes(M, K, Md)
             self._ws = self._torch.empty(nbytes, dtype=self._torch.uint8,
                                          device=f"cuda:{self.device}")
             self._check(self.lib.gmco_bind_workspace(self._ctx, C.c_void_p(self._ws.data_ptr()),
                                                      nbytes), "bind_workspace")
-        cs = gmco_case(K, _dptr(dw), M, _dptr(pts), grp.ctypes.data_as(C.POINTER(C.c_int32)), G,
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+        cs = gmco_case(K, _dptr(dw), M, _dptr(pts), ip(grp), G,
                        _dptr(prm), _dptr(vol), float(prescription_gy), int(target_group),
-                       _dptr(Dr))
+                       _dptr(Dr), ip(gorg), O if gorg is not None else 0, Md, _dptr(dxyz), ip(dorg))
         self._check(self.lib.gmco_load_case(self._ctx, C.byref(cs)), "load_case")
-        self.K, self.M, self.G = K, M, G
+        self.K, self.M, self.G, self.O = K, M, G, O
         self.P = 0
 
     def load(self, case, group_params, target_group: int = 0):
-        """Load a `cases.Case`-like object (dwell_xyz, pt_xyz, group, volume_cc)."""
+        """Load a `cases.Case`-like object (dwell_xyz, pt_xyz, group, volume_cc,
+        and optionally group_organ, dvh_xyz, dvh_organ)."""
         self.load_case(case.dwell_xyz, case.pt_xyz, case.group, group_params, case.volume_cc,
-                       case.prescription_gy, target_group)
+                       case.prescription_gy, target_group,
+                       group_organ=getattr(case, "group_organ", None),
+                       dvh_xyz=getattr(case, "dvh_xyz", None),
+                       dvh_organ=getattr(case, "dvh_organ", None))
 
     def set_weights(self, W, t0=None):
         W = _f64(W)
         P = W.shape[0]
-        if W.shape != (P, self.G):
-            raise ValueError(f"W must be (P, {self.G})")
+        if W.shape != (P, self.O):
+            raise ValueError(f"W must be (P, {self.O})")
         t0a = _f64(t0, (P, self.K)) if t0 is not None else None
         self._check(self.lib.gmco_set_weights(self._ctx, P, _dptr(W), _dptr(t0a)), "set_weights")
         self.P = P
@@ -288,7 +313,7 @@ class Planner:
     def metrics(self) -> dict:
         arr = (gmco_plan_metrics * self.P)()
         self._check(self.lib.gmco_get_metrics(self._ctx, arr), "get_metrics")
-        G = self.G
+        G = self.O
         out = {
             "F_run": np.array([m.F_run for m in arr]),
             "F64": np.array([m.F64 for m in arr]),
@@ -330,7 +355,7 @@ class Planner:
         return int(best.value), cls, nd.astype(bool), float(frac.value)
 
     def case_features(self) -> np.ndarray:
-        out = np.empty(self.G * 16, dtype=np.float32)
+        out = np.empty(self.O * 16, dtype=np.float32)
         self._check(self.lib.gmco_case_features(self._ctx, out.ctypes.data_as(C.POINTER(C.c_float))),
                     "case_features")
         return out

@@ -19,4 +19,9 @@ SURFACE = np.array([
     [0.0, 0.0, 7.5, 15.0],
 ])
 
+# Both rows per structure, surface first: the 8 parameter groups of a case
+# with surface and volume points (group 2 j + 0 surface, 2 j + 1 volume of
+# structure j).
+SURFACE_VOLUME = np.stack([SURFACE, VOLUME], axis=1).reshape(8, 4)
+
 PRESCRIPTION_GY = 15.0

@@ -21,6 +21,7 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 // Byte offsets of every device array inside the arena.
 struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
+  size_t gorg, D64d, dstage, dperm, doff, dcnt;
   size_t Wst, t0st, xst, Fst, gst;
   size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, flag, slot, rt,
       split_tab;
@@ -30,6 +31,7 @@ struct Layout {
 
 struct Dims {
   int M = 0, K = 0, Mp = 0, Kp = 0, Pp = 0, S = 1, ntiles = 1, nblocks = 0;
+  int Md = 0, Mdp = 0;  // DVH points (0: none), padded
   int S_cap = 1;      // split counts up to this fit the partial buffers (autotuning range)
   int S_tuned = 0;    // split set by the caller or the autotuner, 0 = heuristic
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
@@ -82,10 +84,11 @@ struct gmco_ctx {
 
   Dims dim;
   Layout lay{};
-  int G = 0;
+  int G = 0;             // parameter groups (rows of eq. 1)
+  int O = 0;             // organs: hidden weights, point counts, metrics
   double rx = 0.0;
   int target = 0;
-  std::vector<int> counts, offsets, perm;  // host copies
+  std::vector<int> counts, offsets, perm;  // host copies; offsets / counts per organ
   bool case_loaded = false;
   bool has_points = false;  // point positions were given (features need them)
   int P = 0;              // current batch, 0 = none
@@ -126,10 +129,12 @@ bool dtype_available(const int ctx_dtype, int dtype) {
          dtype == GMCO_DTYPE_F32_CHUNK64 || dtype == ctx_dtype;
 }
 
-Dims make_dims(int M, int K, int Pmax, int n_cu) {
+Dims make_dims(int M, int K, int Pmax, int n_cu, int Md) {
   Dims d;
   d.M = M;
   d.K = K;
+  d.Md = Md;
+  d.Mdp = Md > 0 ? round_up(Md, kMAlign) : 0;
   d.Kp = round_up(K, kKAlign);
   d.Mp = round_up(M, kMAlign);
   d.nblocks = d.Mp / kBM;
@@ -174,6 +179,12 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.goff = take(kGmax * 4);
   L.gcnt = take(kGmax * 4);
   L.counts = take(kGmax * 4);
+  L.gorg = take(kGmax * 4);
+  L.D64d = take((size_t)d.Mdp * d.Kp * 8);
+  L.dstage = take((size_t)d.Md * 3 * 8);
+  L.dperm = take((size_t)d.Md * 4);
+  L.doff = take(kGmax * 4);
+  L.dcnt = take(kGmax * 4);
   L.t_bar = take(8);
   L.Wst = take((size_t)Pmax * kGmax * 8);
   L.t0st = take((size_t)Pmax * d.K * 8);
@@ -201,8 +212,10 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.active = take(2 * sizeof(int));
   L.work = take(2 * sizeof(unsigned long long));
   L.t64 = take(PK * 8);
-  // final doses (Pp x Mp); an FP8 context also widens its matrix (Mp x Kp) here
-  L.d64 = take((size_t)std::max(d.Pp, dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp * 8);
+  // final doses (Pp x Mp, then Pp x Mdp for the DVH points); an FP8 context
+  // also widens its matrix (Mp x Kp) here
+  L.d64 = take(std::max((size_t)d.Pp * std::max(d.Mp, d.Mdp),
+                        (size_t)(dtype == GMCO_DTYPE_FP8 ? d.Kp : 0) * d.Mp) * 8);
   L.metrics = take((size_t)d.Pp * sizeof(gmco_plan_metrics));
   L.hist = take(kGmax * 16 * 4);
   L.sel = take((size_t)d.Pp * 3 * 4 + 16);
@@ -389,9 +402,9 @@ int gmco_set_stream(gmco_ctx* c, void* stream) {
   return GMCO_OK;
 }
 
-int gmco_workspace_bytes(const gmco_ctx* c, int M, int K, size_t* bytes) {
-  if (!c || !bytes || M < 1 || K < 1 || K > GMCO_MAX_DWELLS) return GMCO_EINVAL;
-  const Dims d = make_dims(M, K, c->Pmax, c->n_cu);
+int gmco_workspace_bytes(const gmco_ctx* c, int M, int K, int Md, size_t* bytes) {
+  if (!c || !bytes || M < 1 || K < 1 || K > GMCO_MAX_DWELLS || Md < 0) return GMCO_EINVAL;
+  const Dims d = make_dims(M, K, c->Pmax, c->n_cu, Md);
   *bytes = make_layout(d, kGmax, c->m, c->dtype, c->Pmax).total;
   return GMCO_OK;
 }
@@ -413,7 +426,25 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
     return fail(c, GMCO_EINVAL, "missing case array");
   if (!(cs->prescription_gy > 0.0) || !std::isfinite(cs->prescription_gy))
     return fail(c, GMCO_EINVAL, "prescription must be > 0");
-  if (cs->target_group < 0 || cs->target_group >= G) return fail(c, GMCO_EINVAL, "target_group out of range");
+  // organs: the hidden weight and the point count of eq. (obj) are per organ
+  const int O = cs->group_organ ? cs->n_organs : G;
+  if (O < 1 || O > G) return fail(c, GMCO_EINVAL, "n_organs must be 1..n_groups");
+  std::vector<int> gorg(kGmax, 0);
+  for (int j = 0; j < G; ++j) {
+    gorg[j] = cs->group_organ ? cs->group_organ[j] : j;
+    if (gorg[j] < 0 || gorg[j] >= O) return fail(c, GMCO_EINVAL, "group_organ out of range");
+  }
+  const int Md = cs->n_dvh_points;
+  if (Md < 0) return fail(c, GMCO_EINVAL, "n_dvh_points must be >= 0");
+  if (Md > 0 && (!cs->dvh_xyz || !cs->dvh_organ)) return fail(c, GMCO_EINVAL, "DVH points need dvh_xyz and dvh_organ");
+  if (Md > 0 && !finite_all(cs->dvh_xyz, (size_t)Md * 3)) return fail(c, GMCO_EINVAL, "non-finite DVH point position");
+  std::vector<int> dcounts(kGmax, 0);
+  for (int i = 0; i < Md; ++i) {
+    const int o = cs->dvh_organ[i];
+    if (o < 0 || o >= O) return fail(c, GMCO_EINVAL, "dvh_organ out of range");
+    dcounts[o] += 1;
+  }
+  if (cs->target_group < 0 || cs->target_group >= O) return fail(c, GMCO_EINVAL, "target_group out of range");
   if (!finite_all(cs->group_params, (size_t)G * 4)) return fail(c, GMCO_EINVAL, "non-finite group parameter");
   for (int j = 0; j < G; ++j) {
     const double* p = cs->group_params + 4 * j;
@@ -431,10 +462,12 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
     if (g < 0 || g >= G) return fail(c, GMCO_EINVAL, "group index out of range");
     counts[g] += 1;
   }
-  if (counts[cs->target_group] == 0) return fail(c, GMCO_EINVAL, "target structure has no points");
+  std::vector<int> ocounts(kGmax, 0);
+  for (int j = 0; j < G; ++j) ocounts[gorg[j]] += counts[j];
+  if (ocounts[cs->target_group] == 0) return fail(c, GMCO_EINVAL, "target structure has no points");
 
   GMCO_HIP(c, hipSetDevice(c->device));
-  const Dims d = make_dims(M, K, c->Pmax, c->n_cu);
+  const Dims d = make_dims(M, K, c->Pmax, c->n_cu, Md);
   const Layout L = make_layout(d, G, c->m, c->dtype, c->Pmax);
   // arena: bound workspace, else a library allocation (reused when big enough)
   if (c->bound) {
@@ -461,22 +494,32 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   c->dim = d;
   c->lay = L;
   c->G = G;
+  c->O = O;
   c->rx = cs->prescription_gy;
   c->target = cs->target_group;
   c->case_loaded = false;
   c->P = 0;
 
-  // points grouped by structure (stable), so every structure is one range
-  c->counts = counts;
+  // points ordered by organ, then group (stable): every organ is one range
+  std::vector<int> kcur(kGmax * kGmax + 1, 0);  // (organ, group) key offsets
+  for (int j = 0; j < G; ++j) kcur[gorg[j] * kGmax + j + 1] += counts[j];
+  for (int k = 1; k <= kGmax * kGmax; ++k) kcur[k] += kcur[k - 1];
+  c->counts = ocounts;
   c->offsets.assign(kGmax, 0);
-  for (int j = 1; j < kGmax; ++j) c->offsets[j] = c->offsets[j - 1] + counts[j - 1];
+  for (int o = 0; o < kGmax; ++o) c->offsets[o] = kcur[o * kGmax];
   c->perm.assign(M, 0);
-  {
-    std::vector<int> cur(c->offsets);
-    for (int i = 0; i < M; ++i) c->perm[cur[cs->group[i]]++] = i;
-  }
+  for (int i = 0; i < M; ++i) c->perm[kcur[gorg[cs->group[i]] * kGmax + cs->group[i]]++] = i;
   std::vector<int> grp(d.Mp, kGmax);
   for (int i = 0; i < M; ++i) grp[i] = cs->group[c->perm[i]];
+  std::vector<int> norm(kGmax, 0);  // N_pnt of each group's organ
+  for (int j = 0; j < G; ++j) norm[j] = ocounts[gorg[j]];
+  // DVH points ordered by organ
+  std::vector<int> doff(kGmax, 0), dperm(Md, 0);
+  for (int o = 1; o < kGmax; ++o) doff[o] = doff[o - 1] + dcounts[o - 1];
+  {
+    std::vector<int> cur(doff);
+    for (int i = 0; i < Md; ++i) dperm[cur[cs->dvh_organ[i]]++] = i;
+  }
 
   double* stage = c->at<double>(L.stage);
   double* st_D = stage;                         // M*K
@@ -490,12 +533,19 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   if (cs->dose_rate && (rc = copy_h2d(c, st_D, cs->dose_rate, (size_t)M * K * 8))) return rc;
   std::vector<double> gp(kGmax * 4, 0.0), vol(kGmax, 0.0);
   std::copy(cs->group_params, cs->group_params + 4 * G, gp.begin());
-  if (cs->group_volume_cc) std::copy(cs->group_volume_cc, cs->group_volume_cc + G, vol.begin());
+  if (cs->group_volume_cc) std::copy(cs->group_volume_cc, cs->group_volume_cc + O, vol.begin());
   if ((rc = copy_h2d(c, c->at<void>(L.gparams), gp.data(), gp.size() * 8))) return rc;
   if ((rc = copy_h2d(c, c->at<void>(L.volume), vol.data(), vol.size() * 8))) return rc;
   if ((rc = copy_h2d(c, c->at<void>(L.goff), c->offsets.data(), kGmax * 4))) return rc;
-  if ((rc = copy_h2d(c, c->at<void>(L.gcnt), counts.data(), kGmax * 4))) return rc;
-  if ((rc = copy_h2d(c, c->at<void>(L.counts), counts.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.gcnt), ocounts.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.counts), norm.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.gorg), gorg.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.doff), doff.data(), kGmax * 4))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.dcnt), dcounts.data(), kGmax * 4))) return rc;
+  if (Md > 0) {
+    if ((rc = copy_h2d(c, c->at<void>(L.dperm), dperm.data(), (size_t)Md * 4))) return rc;
+    if ((rc = copy_h2d(c, c->at<void>(L.dstage), cs->dvh_xyz, (size_t)Md * 3 * 8))) return rc;
+  }
   // (host vectors of this call stay alive until the stream synchronisation below)
   std::vector<int> split_tab(d.split16);
   split_tab.insert(split_tab.end(), d.split32.begin(), d.split32.end());
@@ -511,8 +561,11 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   GMCO_HIP(c, launch_cast_dose(c->at<double>(L.D64), d.Mp, d.Kp, c->dtype, c->at<float>(L.D32),
                                c->at<void>(L.Dlp), c->at<void>(L.DTlp), c->at<float>(L.colscale),
                                c->stream));
+  if (Md > 0)  // the DVH points: point-source law, organ order
+    GMCO_HIP(c, launch_dose_rate(st_dw, c->at<double>(L.dstage), nullptr, c->at<int>(L.dperm), Md, K,
+                                 d.Mdp, d.Kp, c->at<double>(L.D64d), c->stream));
   const int r0 = c->offsets[cs->target_group];
-  GMCO_HIP(c, launch_start_time(c->at<double>(L.D64), d.Kp, r0, r0 + counts[cs->target_group], c->rx,
+  GMCO_HIP(c, launch_start_time(c->at<double>(L.D64), d.Kp, r0, r0 + ocounts[cs->target_group], c->rx,
                                 c->at<double>(L.t_bar), c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
   c->has_points = cs->point_xyz != nullptr;
@@ -524,8 +577,8 @@ int gmco_set_weights(gmco_ctx* c, int P, const double* W, const double* t0) {
   if (!c || !W) return GMCO_EINVAL;
   if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
   if (P < 1 || P > c->Pmax) return fail(c, GMCO_EINVAL, "n_plans out of 1..max_plans");
-  const int G = c->G, K = c->dim.K;
-  for (size_t i = 0; i < (size_t)P * G; ++i)
+  const int O = c->O, K = c->dim.K;
+  for (size_t i = 0; i < (size_t)P * O; ++i)
     if (!std::isfinite(W[i]) || W[i] < 0.0) return fail(c, GMCO_EINVAL, "weights must be finite and >= 0");
   if (t0) {
     for (size_t i = 0; i < (size_t)P * K; ++i)
@@ -534,10 +587,11 @@ int gmco_set_weights(gmco_ctx* c, int P, const double* W, const double* t0) {
   GMCO_HIP(c, hipSetDevice(c->device));
   const Layout& L = c->lay;
   int rc;
-  if ((rc = copy_h2d(c, c->at<void>(L.Wst), W, (size_t)P * G * 8))) return rc;
+  if ((rc = copy_h2d(c, c->at<void>(L.Wst), W, (size_t)P * O * 8))) return rc;
   if (t0 && (rc = copy_h2d(c, c->at<void>(L.t0st), t0, (size_t)P * K * 8))) return rc;
   GMCO_HIP(c, launch_init_plans(P, c->dim.Pp, K, c->dim.Kp, t0 ? c->at<double>(L.t0st) : nullptr,
-                                c->at<double>(L.t_bar), c->at<double>(L.Wst), G, c->at<int>(L.counts),
+                                c->at<double>(L.t_bar), c->at<double>(L.Wst), c->G, O, c->at<int>(L.gorg),
+                                c->at<int>(L.counts),
                                 c->at<float>(L.xt), c->at<float>(L.x), c->at<float>(L.wn),
                                 c->at<double>(L.W64), c->at<PlanState>(L.ps), c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
@@ -850,14 +904,43 @@ int gmco_get_weights_x(gmco_ctx* c, double* x) {
 }
 
 namespace {
+// FP64 metrics at the current t: doses of the optimisation points give F and
+// the individual objectives (and the DVH metrics when the case has no DVH
+// point set); the DVH points, when given, then give the DVH metrics.
 int compute_metrics(gmco_ctx* c) {
   const Layout& L = c->lay;
   const Dims& d = c->dim;
+  const bool dvh = d.Md > 0;
+  MetricsArgs m{};
+  m.W64 = c->at<double>(L.W64);
+  m.ps = c->at<PlanState>(L.ps);
+  m.P = c->P;
+  m.O = c->O;
+  m.grp = c->at<int>(L.grp);
+  m.gparams = c->at<double>(L.gparams);
+  m.volume_cc = c->at<double>(L.volume);
+  m.rx = c->rx;
+  m.out = c->at<gmco_plan_metrics>(L.metrics);
   GMCO_HIP(c, launch_export_t(c->at<float>(L.x), d.Pp, d.K, d.Kp, c->at<double>(L.t64), d.Kp, c->stream));
   GMCO_HIP(c, launch_dose64(c->at<double>(L.D64), c->at<double>(L.t64), d.Mp, d.Kp, d.Pp, c->at<double>(L.d64), c->stream));
-  GMCO_HIP(c, launch_metrics(c->at<double>(L.d64), c->at<double>(L.W64), c->at<PlanState>(L.ps), c->P, d.Mp,
-                             c->at<int>(L.goff), c->at<int>(L.gcnt), c->G, c->at<double>(L.gparams),
-                             c->at<double>(L.volume), c->rx, c->at<gmco_plan_metrics>(L.metrics), c->stream));
+  m.d64 = c->at<double>(L.d64);
+  m.ld = d.Mp;
+  m.off = c->at<int>(L.goff);
+  m.cnt = c->at<int>(L.gcnt);
+  m.objective = 1;
+  m.dvh = dvh ? 0 : 1;
+  GMCO_HIP(c, launch_metrics(m, c->stream));
+  if (dvh) {
+    GMCO_HIP(c, launch_dose64(c->at<double>(L.D64d), c->at<double>(L.t64), d.Mdp, d.Kp, d.Pp,
+                              c->at<double>(L.d64), c->stream));
+    m.ld = d.Mdp;
+    m.off = c->at<int>(L.doff);
+    m.cnt = c->at<int>(L.dcnt);
+    m.objective = 0;
+    m.dvh = 1;
+    GMCO_HIP(c, launch_metrics(m, c->stream));
+  }
+  GMCO_HIP(c, launch_metrics_final(m, c->stream));
   return GMCO_OK;
 }
 }  // namespace
@@ -869,7 +952,7 @@ int gmco_select_plan(gmco_ctx* c, const gmco_select_opts* opts, int* best, int* 
   gmco_select_opts o{0, 1, 2, 3, 90.0, 95.0, 118.0, 1.0, 1.0};
   if (opts) o = *opts;
   for (int j : {o.target, o.urethra, o.bladder, o.rectum})
-    if (j < 0 || j >= c->G) return fail(c, GMCO_EINVAL, "structure index out of range");
+    if (j < 0 || j >= c->O) return fail(c, GMCO_EINVAL, "structure index out of range");
   GMCO_HIP(c, hipSetDevice(c->device));
   int rc = compute_metrics(c);
   if (rc) return rc;
@@ -878,7 +961,7 @@ int gmco_select_plan(gmco_ctx* c, const gmco_select_opts* opts, int* best, int* 
   int* tu = cls + Pp;
   int* nd = tu + Pp;
   int* res = nd + Pp;
-  GMCO_HIP(c, launch_select(c->at<gmco_plan_metrics>(c->lay.metrics), P, c->G, o, cls, tu, nd, res, c->stream));
+  GMCO_HIP(c, launch_select(c->at<gmco_plan_metrics>(c->lay.metrics), P, c->O, o, cls, tu, nd, res, c->stream));
   int h[2] = {0, 0};
   GMCO_HIP(c, hipMemcpyAsync(h, res, 8, hipMemcpyDeviceToHost, c->stream));
   if (plan_class) GMCO_HIP(c, hipMemcpyAsync(plan_class, cls, (size_t)P * 4, hipMemcpyDeviceToHost, c->stream));
@@ -894,12 +977,8 @@ int gmco_get_metrics(gmco_ctx* c, gmco_plan_metrics* out) {
   if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
   GMCO_HIP(c, hipSetDevice(c->device));
   const Layout& L = c->lay;
-  const Dims& d = c->dim;
-  GMCO_HIP(c, launch_export_t(c->at<float>(L.x), d.Pp, d.K, d.Kp, c->at<double>(L.t64), d.Kp, c->stream));
-  GMCO_HIP(c, launch_dose64(c->at<double>(L.D64), c->at<double>(L.t64), d.Mp, d.Kp, d.Pp, c->at<double>(L.d64), c->stream));
-  GMCO_HIP(c, launch_metrics(c->at<double>(L.d64), c->at<double>(L.W64), c->at<PlanState>(L.ps), c->P, d.Mp,
-                             c->at<int>(L.goff), c->at<int>(L.gcnt), c->G, c->at<double>(L.gparams),
-                             c->at<double>(L.volume), c->rx, c->at<gmco_plan_metrics>(L.metrics), c->stream));
+  const int rc = compute_metrics(c);
+  if (rc) return rc;
   GMCO_HIP(c, hipMemcpyAsync(out, c->at<void>(L.metrics), (size_t)c->P * sizeof(gmco_plan_metrics),
                              hipMemcpyDeviceToHost, c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
@@ -970,8 +1049,8 @@ int gmco_case_features(gmco_ctx* c, float* out) {
   const double* dw = stage + (size_t)d.M * d.K;
   const double* pts = dw + (size_t)d.K * 3;
   GMCO_HIP(c, launch_features(dw, pts, c->at<int>(L.perm), c->at<int>(L.goff), c->at<int>(L.gcnt), d.K,
-                              c->G, c->at<unsigned>(L.hist), c->at<float>(L.feat), c->stream));
-  GMCO_HIP(c, hipMemcpyAsync(out, c->at<void>(L.feat), (size_t)c->G * 16 * 4, hipMemcpyDeviceToHost, c->stream));
+                              c->O, c->at<unsigned>(L.hist), c->at<float>(L.feat), c->stream));
+  GMCO_HIP(c, hipMemcpyAsync(out, c->at<void>(L.feat), (size_t)c->O * 16 * 4, hipMemcpyDeviceToHost, c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
   return GMCO_OK;
 }

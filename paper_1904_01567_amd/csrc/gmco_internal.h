@@ -128,8 +128,9 @@ hipError_t launch_widen_fp8(const void* D8, const float* colscale, int Mp, int K
 hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_end,
                              double prescription, double* t_bar, hipStream_t st);
 hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, const double* t_bar,
-                             const double* W, int G, const int* counts, float* xt, float* x,
-                             float* wn, double* W64, PlanState* ps, hipStream_t st);
+                             const double* W, int G, int O, const int* gorg, const int* norm,
+                             float* xt, float* x, float* wn, double* W64, PlanState* ps,
+                             hipStream_t st);
 hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t st);
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
@@ -145,10 +146,27 @@ hipError_t launch_x_to_device(const double* x_host_dev, int P, int Pp, int K, in
                               hipStream_t st);
 hipError_t launch_dose64(const double* D64, const double* t64, int Mp, int Kp, int Pp,
                          double* d64, hipStream_t st);
-hipError_t launch_metrics(const double* d64, const double* W64, const PlanState* ps, int P,
-                          int Mp, const int* goff, const int* gcnt, int G, const double* gparams,
-                          const double* volume_cc, double prescription, gmco_plan_metrics* out,
-                          hipStream_t st);
+// One pass of the per-organ metrics over the doses d64 (P rows of stride ld)
+// of a point set whose organ o is the range off[o] .. off[o] + cnt[o]:
+// objective != 0 adds the individual objectives (eq. 1 with each point's
+// group parameters; the optimisation points), dvh != 0 the DVH metrics.
+struct MetricsArgs {
+  const double* d64;
+  int ld;
+  const int* off;
+  const int* cnt;
+  const int* grp;          // group of each optimisation point
+  const double* gparams;   // [kGmax][4]
+  const double* volume_cc; // per organ
+  const double* W64;       // [Pp][kGmax] hidden weights per organ
+  const PlanState* ps;
+  int P, O;
+  int objective, dvh;
+  double rx;
+  gmco_plan_metrics* out;
+};
+hipError_t launch_metrics(const MetricsArgs& m, hipStream_t st);
+hipError_t launch_metrics_final(const MetricsArgs& m, hipStream_t st);
 
 hipError_t launch_select(const gmco_plan_metrics* m, int P, int G, const gmco_select_opts& o, int* cls,
                          int* meets_tu, int* nd, int* out, hipStream_t st);

@@ -82,45 +82,54 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// One workgroup per (plan, structure).
-__global__ __launch_bounds__(256) void k_metrics_group(
-    const double* __restrict__ d64, int P, int Mp, const int* __restrict__ goff,
-    const int* __restrict__ gcnt, int G, const double* __restrict__ gparams,
-    const double* __restrict__ volume_cc, double rx, gmco_plan_metrics* __restrict__ out) {
+// One workgroup per (plan, organ): a pass over the organ's points of one
+// point set (MetricsArgs).  The individual objective f_j = (1/N_j) sum f_i
+// takes each point's own group parameters (surface and volume rows of one
+// organ share the organ's N_j); the DVH metrics follow the definitions of
+// Sec. 2.3.1 (V_x counts d >= x % Rx; D_x is the k-th hottest dose,
+// k = max(1, ceil(x N / 100)), by radix select on the FP64 bit patterns).
+__global__ __launch_bounds__(256) void k_metrics_group(MetricsArgs a) {
   __shared__ double red[256];
   __shared__ unsigned int h10[256], h90[256];
   __shared__ SelectState sel[2];
   const int p = blockIdx.x;
   const int j = blockIdx.y;
-  if (p >= P) return;
-  gmco_plan_metrics* m = out + p;
-  if (j >= G) {
+  if (p >= a.P) return;
+  gmco_plan_metrics* m = a.out + p;
+  if (j >= a.O) {
     if (threadIdx.x == 0 && j < kGmax) {
-      m->f_organ[j] = 0.0;
-      m->V100_pct[j] = 0.0;
-      m->V75_cc[j] = 0.0;
-      m->D10_pct[j] = 0.0;
-      m->D90_pct[j] = 0.0;
+      if (a.objective) m->f_organ[j] = 0.0;
+      if (a.dvh) {
+        m->V100_pct[j] = 0.0;
+        m->V75_cc[j] = 0.0;
+        m->D10_pct[j] = 0.0;
+        m->D90_pct[j] = 0.0;
+      }
     }
     return;
   }
-  const int N = gcnt[j];
-  const double* __restrict__ d = d64 + (size_t)p * Mp + goff[j];
-  const double wmin = gparams[4 * j + 0], dmin = gparams[4 * j + 1];
-  const double dmax = gparams[4 * j + 2], wmax = gparams[4 * j + 3];
-  const double thr100 = rx, thr75 = 0.75 * rx;
+  const int N = a.cnt[j];
+  const int o0 = a.off[j];
+  const double* __restrict__ d = a.d64 + (size_t)p * a.ld + o0;
+  const double thr100 = a.rx, thr75 = 0.75 * a.rx;
 
   double fs = 0.0, c100 = 0.0, c75 = 0.0;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const double v = d[i];
-    if (v < dmin) fs += wmin * ((dmin - v) * (dmin - v));
-    else if (v > dmax) fs += wmax * ((v - dmax) * (v - dmax));
+    if (a.objective) {
+      const double* prm = a.gparams + 4 * a.grp[o0 + i];
+      const double wmin = prm[0], dmin = prm[1], dmax = prm[2], wmax = prm[3];
+      if (v < dmin) fs += wmin * ((dmin - v) * (dmin - v));
+      else if (v > dmax) fs += wmax * ((v - dmax) * (v - dmax));
+    }
     c100 += (v >= thr100) ? 1.0 : 0.0;
     c75 += (v >= thr75) ? 1.0 : 0.0;
   }
   fs = block_sum(fs, red);
   c100 = block_sum(c100, red);
   c75 = block_sum(c75, red);
+  if (a.objective && threadIdx.x == 0) m->f_organ[j] = fs / (N > 0 ? (double)N : 1.0);
+  if (!a.dvh) return;
 
   // D10 / D90: k = max(1, ceil(x N / 100)) in integers
   if (threadIdx.x == 0) {
@@ -166,21 +175,20 @@ __global__ __launch_bounds__(256) void k_metrics_group(
   }
   if (threadIdx.x == 0) {
     const double n = N > 0 ? (double)N : 1.0;
-    m->f_organ[j] = fs / n;
     m->V100_pct[j] = 100.0 * (c100 / n);
-    m->V75_cc[j] = (volume_cc ? volume_cc[j] : 0.0) * (c75 / n);
-    m->D10_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[0].prefix) / rx : 0.0;
-    m->D90_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[1].prefix) / rx : 0.0;
+    m->V75_cc[j] = (a.volume_cc ? a.volume_cc[j] : 0.0) * (c75 / n);
+    m->D10_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[0].prefix) / a.rx : 0.0;
+    m->D90_pct[j] = N > 0 ? 100.0 * __longlong_as_double((long long)sel[1].prefix) / a.rx : 0.0;
   }
 }
 
 __global__ void k_metrics_final(const double* __restrict__ W64, const PlanState* __restrict__ ps,
-                                int P, int G, gmco_plan_metrics* __restrict__ out) {
+                                int P, int O, gmco_plan_metrics* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   gmco_plan_metrics* m = out + p;
   double F = 0.0;
-  for (int j = 0; j < G; ++j) F += W64[(size_t)p * kGmax + j] * m->f_organ[j];
+  for (int j = 0; j < O; ++j) F += W64[(size_t)p * kGmax + j] * m->f_organ[j];
   m->F64 = F;
   m->F_run = ps[p].F;
   m->iterations = ps[p].iter;
@@ -324,16 +332,16 @@ hipError_t launch_dose64(const double* D64, const double* t64, int Mp, int Kp, i
   return hipGetLastError();
 }
 
-hipError_t launch_metrics(const double* d64, const double* W64, const PlanState* ps, int P,
-                          int Mp, const int* goff, const int* gcnt, int G, const double* gparams,
-                          const double* volume_cc, double prescription, gmco_plan_metrics* out,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_metrics_group, dim3(P, kGmax), dim3(256), 0, st, d64, P, Mp, goff, gcnt,
-                     G, gparams, volume_cc, prescription, out);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_metrics_final, dim3((P + 127) / 128), dim3(128), 0, st, W64, ps, P, G,
-                     out);
+hipError_t launch_metrics(const MetricsArgs& m, hipStream_t st) {
+  if (m.P < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_metrics_group, dim3(m.P, kGmax), dim3(256), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics_final(const MetricsArgs& m, hipStream_t st) {
+  if (m.P < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_metrics_final, dim3((m.P + 127) / 128), dim3(128), 0, st, m.W64, m.ps, m.P,
+                     m.O, m.out);
   return hipGetLastError();
 }
 

@@ -125,9 +125,12 @@ __global__ void k_start_time(const double* __restrict__ D64, int Kp, int r0, int
 
 // Start point and weights of every plan slot.  Inactive slots (p >= P) get
 // zero weights and the INACTIVE state.
+// W is P x O hidden weights (one per organ); group j of organ gorg[j] gets
+// w / N_pnt of its organ (eq. (obj)).
 __global__ void k_init_plans(int P, int Pp, int K, int Kp, const double* __restrict__ t0,
                              const double* __restrict__ t_bar, const double* __restrict__ W,
-                             int G, const int* __restrict__ counts, float* __restrict__ xt,
+                             int G, int O, const int* __restrict__ gorg,
+                             const int* __restrict__ norm, float* __restrict__ xt,
                              float* __restrict__ x, float* __restrict__ wn,
                              double* __restrict__ W64, PlanState* __restrict__ ps) {
   const int p = blockIdx.x;
@@ -145,10 +148,10 @@ __global__ void k_init_plans(int P, int Pp, int K, int Kp, const double* __restr
   }
   if (threadIdx.x < kGmax) {
     const int j = threadIdx.x;
+    W64[(size_t)p * kGmax + j] = (live && j < O) ? W[(size_t)p * O + j] : 0.0;
     double w = 0.0;
-    if (live && j < G) w = W[(size_t)p * G + j];
-    W64[(size_t)p * kGmax + j] = w;
-    wn[(size_t)p * kGmax + j] = (j < G && counts[j] > 0) ? (float)(w / (double)counts[j]) : 0.f;
+    if (live && j < G) w = W[(size_t)p * O + gorg[j]];
+    wn[(size_t)p * kGmax + j] = (j < G && norm[j] > 0) ? (float)(w / (double)norm[j]) : 0.f;
   }
   if (threadIdx.x == 0) {
     PlanState s;
@@ -225,10 +228,11 @@ hipError_t launch_start_time(const double* D64, int Kp, int row_begin, int row_e
 }
 
 hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, const double* t_bar,
-                             const double* W, int G, const int* counts, float* xt, float* x,
-                             float* wn, double* W64, PlanState* ps, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_plans, dim3(Pp), dim3(128), 0, st, P, Pp, K, Kp, t0, t_bar, W, G,
-                     counts, xt, x, wn, W64, ps);
+                             const double* W, int G, int O, const int* gorg, const int* norm,
+                             float* xt, float* x, float* wn, double* W64, PlanState* ps,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_init_plans, dim3(Pp), dim3(128), 0, st, P, Pp, K, Kp, t0, t_bar, W, G, O,
+                     gorg, norm, xt, x, wn, W64, ps);
   return hipGetLastError();
 }
 

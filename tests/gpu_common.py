@@ -29,10 +29,10 @@ def announce(msg: str):
     sys.stdout.flush()
 
 
-def planner(case, W, dtype="f32", t0=None, max_plans=None, history=10):
+def planner(case, W, dtype="f32", t0=None, max_plans=None, history=10, params=None):
     from paper_1904_01567_amd import Planner
     pl = Planner(dtype=dtype, history=history, max_plans=max_plans or W.shape[0])
-    pl.load(case, PARAMS)
+    pl.load(case, PARAMS if params is None else params)
     pl.set_weights(W, t0)
     return pl
 

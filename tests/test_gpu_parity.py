@@ -370,6 +370,81 @@ def test_metrics_match_oracle_at_given_times():
     np.testing.assert_allclose(pl.dwell_times(), t, rtol=0, atol=0)
 
 
+# ---------------------------------------------------------------------------
+# Surface and volume points (8 groups, 4 organs) and a separate DVH point set
+# ---------------------------------------------------------------------------
+SV = O.CLASS_SOLUTION_SV
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32acc64", "bf16"])
+def test_surface_volume_evaluate_matches_oracle(dtype):
+    announce(f"8-group evaluate {dtype}")
+    c = cases.case_sv_small()
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    W = cases.hidden_weights(70, seed=77)  # one weight per organ; 2 tiles
+    organ = O.point_organs(c.group, c.group_organ)
+    t_bar = O.uniform_start_time(D, organ, 15.0)
+    x = np.sqrt(t_bar * (0.2 + 1.6 * cases.uniform_draws((W.shape[0], c.K), seed=78)))
+    pl = planner(c, W, dtype=dtype, params=SV)
+    F, g = pl.evaluate(x)
+    Fr, gr = O.objective_and_gradient_x(D, x, c.group, SV, W, c.group_organ)
+    tf, tg = TOL[dtype]
+    assert np.max(np.abs(F - Fr) / Fr) <= tf
+    assert np.abs(g - gr).max() / np.abs(gr).max() <= tg
+    assert pl.start_time() == pytest.approx(t_bar, rel=1e-12)
+
+
+def test_surface_volume_first_iterations_follow_the_oracle():
+    announce("8-group trajectory")
+    c = cases.case_sv_small()
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    W = cases.hidden_weights(12, seed=79)
+    organ = O.point_organs(c.group, c.group_organ)
+    x0 = np.full((W.shape[0], c.K), np.sqrt(O.uniform_start_time(D, organ, 15.0)))
+    pl = planner(c, W, dtype="f32acc64", params=SV)
+    pl.optimize(max_iter=3)
+    r = O.optimize(D, c.group, SV, W, x0, O.LbfgsOptions(max_iter=3), group_organ=c.group_organ)
+    m = pl.metrics()
+    np.testing.assert_array_equal(m["iterations"], r["iters"])
+    np.testing.assert_array_equal(m["evaluations"], r["evals"])
+    err = np.abs(pl.weights_x() - r["x"]).max(axis=1) / np.abs(r["x"]).max(axis=1)
+    assert err.max() <= 3e-3
+    np.testing.assert_allclose(m["F_run"], r["F"], rtol=6e-5)
+
+
+def test_dvh_point_set_metrics_match_oracle():
+    # F and the individual objectives on the optimisation points, the DVH
+    # metrics on the separate DVH points, per organ, at seeded dwell times.
+    announce("DVH point set metrics")
+    c = cases.case_sv_small()
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    Dd = O.dose_rate_matrix(c.dwell_xyz, c.dvh_xyz)
+    W = cases.hidden_weights(9, seed=80)
+    organ = O.point_organs(c.group, c.group_organ)
+    t_bar = O.uniform_start_time(D, organ, 15.0)
+    t0 = t_bar * (0.3 + 1.4 * cases.uniform_draws((W.shape[0], c.K), seed=81))
+    pl = planner(c, W, params=SV, t0=t0)
+    m = pl.metrics()
+    x32 = np.sqrt(t0).astype(np.float32).astype(np.float64)
+    t = x32 * x32
+    mref = O.plan_metrics(D, t, c.group, SV, W, c.volume_cc, 15.0, c.group_organ,
+                          D_dvh=Dd, dvh_organ=c.dvh_organ)
+    for p in range(W.shape[0]):
+        q = mref[p]
+        assert m["F64"][p] == pytest.approx(q["F"], rel=1e-12)
+        np.testing.assert_allclose(m["f_organ"][p], q["f_organ"], rtol=1e-12, atol=1e-300)
+        np.testing.assert_array_equal(m["V100_pct"][p], q["V100_pct"])
+        np.testing.assert_array_equal(m["V75_cc"][p], q["V75_cc"])
+        np.testing.assert_allclose(m["D10_pct"][p], q["D10_pct"], rtol=1e-13)
+        np.testing.assert_allclose(m["D90_pct"][p], q["D90_pct"], rtol=1e-13)
+    # the selection runs on these per-organ metrics
+    best, cls, nd, frac = pl.select_plan()
+    mlist = [dict(V100_pct=q["V100_pct"], D10_pct=q["D10_pct"], V75_cc=q["V75_cc"]) for q in mref]
+    assert best == O.select_plan(mlist)
+    np.testing.assert_array_equal(cls, [O.plan_class(q) for q in mlist])
+    np.testing.assert_array_equal(nd.astype(bool), O.nondominated(np.array([q["f_organ"] for q in mref])))
+
+
 def test_single_plan_equals_plan_in_batch():
     announce("batch independence")
     c, D = oracle_dose_rate("case_c1")

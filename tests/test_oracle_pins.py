@@ -471,3 +471,90 @@ def test_rtog_classes_and_selection_by_hand():
 def test_nondominated_by_hand():
     f = np.array([[1.0, 2.0], [2.0, 1.0], [2.0, 2.0], [1.0, 2.0], [0.5, 3.0]])
     np.testing.assert_array_equal(O.nondominated(f), [True, True, False, True, True])
+
+
+# ---------------------------------------------------------------------------
+# Surface and volume points (Table 1): groups share their organ's hidden
+# weight and point count in eq. (obj); the DVH metrics may use a separate
+# point set.
+# ---------------------------------------------------------------------------
+def _sv_tiny():
+    c = cases.make_case_sv(3, 3, (5, 8, 4, 4, 3, 4, 3, 4), seed=71, dvh_points=(30, 10, 12, 12))
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    return c, D
+
+
+def test_surface_volume_objective_by_explicit_loops():
+    c, D = _sv_tiny()
+    rng = np.random.default_rng(5)
+    W = cases.hidden_weights(3, seed=9)
+    t = rng.uniform(0.5, 2.0, size=(3, c.K)) * O.uniform_start_time(D, O.point_organs(c.group, c.group_organ), 15.0)
+    prm = O.CLASS_SOLUTION_SV
+    F = O.objective(D, t, c.group, prm, W, c.group_organ)
+    for p in range(3):
+        total = 0.0
+        for o in range(4):
+            members = [i for i in range(c.M) if c.group_organ[c.group[i]] == o]
+            s = 0.0
+            for i in members:
+                d = sum(D[i, l] * t[p, l] for l in range(c.K))
+                wmin, dmin, dmax, wmax = prm[c.group[i]]
+                if d < dmin:
+                    s += wmin * (dmin - d) ** 2
+                elif d > dmax:
+                    s += wmax * (d - dmax) ** 2
+            total += W[p, o] * s / len(members)
+        assert F[p] == pytest.approx(total, rel=1e-12)
+    # the gradient is the derivative of that objective (central differences)
+    x = np.sqrt(t)
+    _, g = O.objective_and_gradient_x(D, x, c.group, prm, W, c.group_organ)
+    for l in (0, c.K // 2, c.K - 1):
+        h = 1e-6 * max(1.0, abs(x[0, l]))
+        xp, xm = x.copy(), x.copy()
+        xp[0, l] += h
+        xm[0, l] -= h
+        fd = (O.objective(D, xp[:1] ** 2, c.group, prm, W[:1], c.group_organ)[0]
+              - O.objective(D, xm[:1] ** 2, c.group, prm, W[:1], c.group_organ)[0]) / (2 * h)
+        assert g[0, l] == pytest.approx(fd, rel=1e-6, abs=1e-9 * abs(g[0]).max())
+
+
+def test_identical_rows_reduce_to_one_group_per_organ():
+    # With the surface row equal to the volume row of every organ, the
+    # 8-group objective is the 4-group objective over the same points with
+    # group = organ: the count N_pnt,j is the organ's, not the group's.
+    c, D = _sv_tiny()
+    W = cases.hidden_weights(4, seed=3)
+    organ = O.point_organs(c.group, c.group_organ)
+    t = np.full((4, c.K), O.uniform_start_time(D, organ, 15.0)) * np.linspace(0.7, 1.4, 4)[:, None]
+    prm8 = np.repeat(O.CLASS_SOLUTION_VOLUME, 2, axis=0)
+    F8 = O.objective(D, t, c.group, prm8, W, c.group_organ)
+    F4 = O.objective(D, t, organ, O.CLASS_SOLUTION_VOLUME, W)
+    np.testing.assert_allclose(F8, F4, rtol=1e-13)
+    np.testing.assert_allclose(O.organ_objectives(D, t, c.group, prm8, c.group_organ),
+                               O.organ_objectives(D, t, organ, O.CLASS_SOLUTION_VOLUME), rtol=1e-13)
+
+
+def test_dvh_point_set_is_separate():
+    c, D = _sv_tiny()
+    W = cases.hidden_weights(2, seed=4)
+    organ = O.point_organs(c.group, c.group_organ)
+    t = np.full((2, c.K), O.uniform_start_time(D, organ, 15.0)) * np.array([[0.9], [1.2]])
+    prm = O.CLASS_SOLUTION_SV
+    base = O.plan_metrics(D, t, c.group, prm, W, c.volume_cc, 15.0, c.group_organ)
+    # the optimisation points as their own DVH set, in reversed order
+    same = O.plan_metrics(D, t, c.group, prm, W, c.volume_cc, 15.0, c.group_organ,
+                          D_dvh=D[::-1], dvh_organ=organ[::-1])
+    Dd = O.dose_rate_matrix(c.dwell_xyz, c.dvh_xyz)
+    other = O.plan_metrics(D, t, c.group, prm, W, c.volume_cc, 15.0, c.group_organ,
+                           D_dvh=Dd, dvh_organ=c.dvh_organ)
+    for b, s, o in zip(base, same, other):
+        for k in ("V100_pct", "V75_cc", "D10_pct", "D90_pct"):
+            np.testing.assert_array_equal(b[k], s[k])
+        # F and the individual objectives always come from the optimisation points
+        assert o["F"] == b["F"]
+        np.testing.assert_array_equal(o["f_organ"], b["f_organ"])
+        # the DVH set's own V100, recounted by hand
+        d = Dd @ t[0] if o is other[0] else Dd @ t[1]
+        for j in range(4):
+            dj = d[c.dvh_organ == j]
+            assert o["V100_pct"][j] == pytest.approx(100.0 * np.count_nonzero(dj >= 15.0) / dj.size, abs=0)
