@@ -349,6 +349,8 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
 
   __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
   __shared__ double sX[2][4][4][64];  // partial doses [half][group][r][lane]
+  __shared__ float sPhi[4][4][64];     // phi of the last block [group][r][lane]
+  __shared__ double sF[4][64];         // F partial of the half-1 waves [group][lane]
   __shared__ float sW[kPT * kGmax];
   __shared__ int sPlan[kPT];
   __shared__ int sScan[NT / 64];
@@ -419,8 +421,8 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
     if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
   }
 
-  float phi_prev[4] = {0.f, 0.f, 0.f, 0.f};
   for (int i = tid; i < kBM * KS; i += NT) sD[1][i] = 0.f;
+  for (int i = tid; i < 4 * 4 * 64; i += NT) (&sPhi[0][0][0])[i] = 0.f;
   if (b_begin < b_end) GMCO_PF64(b_begin);
 #pragma unroll 1
   for (int b = b_begin; b <= b_end; ++b) {
@@ -438,6 +440,11 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
 
     const float* __restrict__ Dc = sD[cur];
     const float* __restrict__ Dp = sD[prv];
+    // phi of block b-1 for the back-projection, written by the two waves of
+    // this plan group (rows 0-1 and 2-3) before the barrier above
+    float phi_prev[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) phi_prev[r] = sPhi[grp][r][lane];
     d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
 #pragma unroll
     for (int k = 0; k < NKH; ++k) {
@@ -456,23 +463,24 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) sX[half][grp][r][lane] = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
     __syncthreads();
-    float phi[4] = {0.f, 0.f, 0.f, 0.f};
+    // eq. 1 on the summed dose: each wave of the group takes two of the four
+    // rows (points q + 4r) and shares phi through LDS; the next iteration's
+    // first barrier orders these writes before their reads
     if (have_cur) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int rr = 0; rr < 2; ++rr) {
+        const int r = 2 * half + rr;
         const double d = sX[0][grp][r][lane] + sX[1][grp][r][lane];
         const int gi = sG[cur][q + 4 * r];
         const float w = (gi < kGmax) ? sW[col * kGmax + gi] : 0.f;
-        // eq. 1 without branches: at most one of the two deviations is nonzero
+        // without branches: at most one of the two deviations is nonzero
         const double lo = fmin(d - sP64[gi][1], 0.0);
         const double hi = fmax(d - sP64[gi][2], 0.0);
         const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
         facc += (double)w * (kap * (lo + hi));
-        phi[r] = (float)((double)w * kap);
+        sPhi[grp][r][lane] = (float)((double)w * kap);
       }
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) phi_prev[r] = phi[r];
   }
 #undef GMCO_PF64
 #undef GMCO_ST64
@@ -484,7 +492,11 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
     *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
         make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
   }
+  // F partial: rows 0-1 (half 0) + rows 2-3 (half 1), then over q
+  if (half == 1) sF[grp][lane] = facc;
+  __syncthreads();
   if (half == 0) {
+    facc += sF[grp][lane];
     facc += __shfl_xor(facc, 16);
     facc += __shfl_xor(facc, 32);
     if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
