@@ -7,13 +7,15 @@ point-source dose law) with a batch of 1,000 hidden-weight vectors
 (log-uniform in [0.1, 10], normalised).  One step is one pass of the whole hot
 path over that batch: upload the weights, run batched L-BFGS (m = 10) for the
 calibrated iteration count, export t = x^2 and compute the FP64 objective and
-DVH metrics of every plan.  Inputs are resident on the GPU before timing.
+DVH metrics of every plan.  Inputs are resident on the GPU before timing.  By
+default the first 500 accepted steps use FP32 matrix ops and the rest the
+FP64-accumulated dose (DEFAULT_LADDER); --dtype runs one arithmetic throughout.
 
 Prints one JSON line: Pareto plans per second (1000 / seconds per step), the
 roofline position of the fused evaluation kernel, and the FP64 oracle timed
 on the host cores on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--dtype f32acc64] [--iters N]
+    python bench.py [--steps K] [--warmup W] [--dtype f32acc64 | --ladder f32:500,f32acc64:2000]
 """
 from __future__ import annotations
 
@@ -35,6 +37,11 @@ TOL_V100 = 0.1      # target V100 difference in percentage points
 # workload meets both tolerances (calibrated with --calibrate against the
 # oracle optima in tests/golden/c2_reference_optima.json).
 TIME_EVERY = 16  # rounds between timed rounds in the timed steps
+# Headline arithmetic: FP32 matrix ops for the first 500 accepted steps, then
+# the FP64-accumulated dose to 2,000 steps (the plan state carries over; plans
+# whose FP32 line search stalled resume).  64/64 sampled plans meet the
+# tolerance, as with the FP64-accumulated dose throughout.
+DEFAULT_LADDER = "f32:500,f32acc64:2000"
 EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k_eval_f32",
                "bf16": "k_eval_bf16", "fp8": "k_eval_fp8"}
 
@@ -54,8 +61,10 @@ PEAK_F32 = 157.3
 
 DTYPE_NAMES = {"f32acc64": "f32 operands, f64-accumulated dose",
                "f32chunk64": "f32 matrix ops, 16-dwell partials accumulated in f64",
-               "f32": "f32", "bf16": "bf16"}
+               "f32": "f32", "bf16": "bf16",
+               "fp8": "fp8 e4m3 dose product, bf16 back-projection"}
 PEAK_BF16 = 2500.0
+PEAK_FP8 = 5000.0
 
 
 def eval_peak_tflops(dtype: str) -> float:
@@ -67,6 +76,8 @@ def eval_peak_tflops(dtype: str) -> float:
         return 2.0 / (1.0 / PEAK_F64 + 1.0 / PEAK_F32)
     if dtype == "bf16":
         return PEAK_BF16
+    if dtype == "fp8":  # FP8 dose product, BF16 back-projection
+        return 2.0 / (1.0 / PEAK_FP8 + 1.0 / PEAK_BF16)
     return PEAK_F32        # f32 and f32chunk64 run both products on FP32 matrix ops
 
 
@@ -374,7 +385,9 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32acc64", choices=["f32acc64", "f32chunk64", "f32", "bf16", "fp8"])
+    ap.add_argument("--dtype", default=None, choices=["f32acc64", "f32chunk64", "f32", "bf16", "fp8"],
+                    help="one stage in this arithmetic (default: the ladder DEFAULT_LADDER; "
+                         "f32acc64 for the other modes)")
     ap.add_argument("--ladder", type=str, default=None,
                     help="precision ladder, e.g. bf16:150,f32acc64:2000 (iteration caps are "
                          "cumulative); the context is created with the first dtype")
@@ -405,6 +418,8 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB buffer once (reference for HBM byte counters)")
     args = ap.parse_args(argv)
+    one_stage = args.dtype is not None
+    args.dtype = args.dtype or "f32acc64"
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -440,6 +455,8 @@ def main(argv=None) -> int:
         return plan_sweep(args)
     if args.surface_volume:
         return surface_volume(args)
+    if not one_stage and not args.ladder:
+        args.ladder = DEFAULT_LADDER
     stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
     if args.ladder:
         stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]
