@@ -293,7 +293,7 @@ int gmco_get_start_time(gmco_ctx* ctx, double* t_bar);
 /* Case features of the learned warm start: for every structure j, the
  * histogram over dwells of the distance from the dwell to the nearest point
  * of j, in 16 bins of 0.25 cm (the last bin open-ended), divided by the dwell
- * count.  out has n_groups x 16 floats.  Needs a case loaded with point
+ * count.  out has n_organs x 16 floats (structures = organs).  Needs a case loaded with point
  * positions.  (Project extension; not in the paper.) */
 int gmco_case_features(gmco_ctx* ctx, float* out);
 

@@ -45,6 +45,23 @@ def test_batched_rounds_match_single_case_runs():
         announce(f"rounds_per_graph={R}: identical to single-case runs")
 
 
+def test_graph_replays_with_early_exit_match_eager():
+    # The relative-variation stop rule stops plans at different rounds; each
+    # captured round compacts its context's running plans on the device, so
+    # the replayed graph must still equal plain launches bit for bit.
+    from paper_1904_01567_amd import optimize_many
+    announce("graph replay with early exit")
+    eager = _planners()
+    graph = _planners()
+    ie = optimize_many(eager, max_iter=400, eps=1e-3, rounds_per_graph=0)
+    ig = optimize_many(graph, max_iter=400, eps=1e-3, rounds_per_graph=6)
+    for a, b, x, y in zip(eager, graph, ie, ig):
+        np.testing.assert_array_equal(a.weights_x(), b.weights_x())
+        np.testing.assert_array_equal(a.metrics()["iterations"], b.metrics()["iterations"])
+        assert x["n_converged"] == y["n_converged"] > 0
+        assert x["eval_work"] == y["eval_work"] < x["rounds"]
+
+
 def test_graph_replays_match_eager_at_every_stage():
     from paper_1904_01567_amd import optimize_many
     announce("graph replays vs eager")
