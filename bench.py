@@ -228,6 +228,47 @@ def surface_volume(args) -> int:
     return 0
 
 
+def warm_start_compare(args) -> int:
+    """Warm-started BF16 form against plain FP32 L-BFGS at equal objective
+    accuracy: train the network on the method's own plans for a few cases of
+    the paper-scale layout, then on held-out cases time how long each form
+    takes until all 1,000 plans are within a relative target of a long
+    FP64-accumulated reference run."""
+    import numpy as np
+
+    import cases
+    from paper_1904_01567_amd import warmstart as ws
+    sizes = [68, 256, 256, 256, 360]
+    stages = [ws.Stage("bf16", 150), ws.Stage("f32acc64", 1000)]
+    t0 = time.perf_counter()
+    Xs, Ys = [], []
+    for i in range(args.train_cases):
+        X, Y = ws.labels_for_case(cases.case_learned(i), cases.weights_learned(i, args.plans), stages)
+        Xs.append(X)
+        Ys.append(Y)
+    X, Y = np.concatenate(Xs), np.concatenate(Ys)
+    t_labels = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = ws.train_network(X, Y, sizes, 30, 1024, 1e-3,
+                                   cases.mlp_init(sizes, seed=7).astype(np.float32),
+                                   lambda n, s, b, e: cases.batch_order(n, s, b, seed=100 + e))
+    t_train = time.perf_counter() - t0
+    targets = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]
+    grid = [10, 20, 40, 60, 80, 120, 160, 240, 320, 480, 640, 960, 1280]
+    rows = []
+    for h in range(args.heldout):
+        idx = 10_000 + h
+        r = ws.time_to_accuracy(net, cases.case_learned(idx), cases.weights_learned(idx, args.plans),
+                                targets, grid, floors=(1e-3, 0.1, 0.3))
+        rows.append({"case": idx, **{k: v["time_to_target"] for k, v in r.items()}})
+        print(f"# held-out {h + 1}/{args.heldout}", file=sys.stderr, flush=True)
+    print(json.dumps({"train_cases": args.train_cases, "plans": args.plans, "label_s": t_labels,
+                      "train_s": t_train, "loss": [losses[0], losses[-1]],
+                      "reference": "f32acc64, 2000 steps, cold start", "targets": targets,
+                      "rows": rows}), flush=True)
+    return 0
+
+
 def plan_sweep(args) -> int:
     """Time and device memory against the number of plans (Fig. 4 of the
     paper): one context per batch size, same case, same iteration cap."""
@@ -412,6 +453,10 @@ def main(argv=None) -> int:
                     help="comma-separated batch sizes: time and device memory at each")
     ap.add_argument("--surface-volume", action="store_true",
                     help="8-group objective with a separate DVH point set (paper-scale layout)")
+    ap.add_argument("--warm-start-compare", action="store_true",
+                    help="warm-started BF16 form vs plain FP32 L-BFGS, time to equal accuracy")
+    ap.add_argument("--train-cases", type=int, default=20)
+    ap.add_argument("--heldout", type=int, default=3)
     ap.add_argument("--precision-report", action="store_true",
                     help="per arithmetic: objective, target V100 and OAR D10 errors of the "
                          "sampled plans against the FP64 oracle optima")
@@ -455,6 +500,8 @@ def main(argv=None) -> int:
         return plan_sweep(args)
     if args.surface_volume:
         return surface_volume(args)
+    if args.warm_start_compare:
+        return warm_start_compare(args)
     if not one_stage and not args.ladder:
         args.ladder = DEFAULT_LADDER
     stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]

@@ -59,11 +59,12 @@ def labels_for_case(case, W, stages, dtype_ctx="bf16", params=None):
     return X, xh.astype(np.float32)
 
 
-def warm_start_times(net: Network, pl: Planner, W: np.ndarray) -> np.ndarray:
-    """t0 for a weight batch on the loaded case, from the network."""
+def warm_start_times(net: Network, pl: Planner, W: np.ndarray, floor: float = X_FLOOR) -> np.ndarray:
+    """t0 for a weight batch on the loaded case, from the network; predicted
+    dwell weights are floored at `floor` (x = 0 is a fixed point)."""
     feats = pl.case_features()
     xh = net.predict(plan_inputs(W, feats)).astype(np.float64)
-    return (np.maximum(xh, X_FLOOR) ** 2) * pl.start_time()
+    return (np.maximum(xh, floor) ** 2) * pl.start_time()
 
 
 def train_network(X, Y, sizes, epochs: int, batch: int, lr: float, init_params, order_fn,
@@ -98,6 +99,53 @@ def compare_cold_warm(net: Network, case, W, checkpoints, dtype_ctx="bf16", para
             ms += info["device_ms"]
             F[n] = pl.metrics()["F64"]
         out[name] = dict(F=F, device_ms=ms)
+    pl.close()
+    return out
+
+
+def _timed_run(pl: Planner, W, t0, stages):
+    """Device ms of the stages (a ladder) from a fresh start, and F_64 after."""
+    pl.set_weights(W, t0)
+    ms = 0.0
+    for k, st in enumerate(stages):
+        ms += pl.optimize(max_iter=st.max_iter, dtype=st.dtype, resume_stopped=k > 0)["device_ms"]
+    return ms, pl.metrics()["F64"]
+
+
+def time_to_accuracy(net: Network, case, W, targets, grid, dtype_ctx="bf16", params=None,
+                     ref_iters=2000, warm_bf16_steps=100, floors=(X_FLOOR,)):
+    """Time for all plans of the batch to come within each relative target of
+    a reference objective (a long FP64-accumulated cold run), for
+      cold: plain FP32 L-BFGS from the uniform start, n steps;
+      warm: the network's start, BF16 for the first warm_bf16_steps steps,
+            then FP32 to n steps.
+    n runs over `grid`; the first n at which every plan meets the target gives
+    the time (device ms of a fresh run of n steps).  None when no n does.
+    One warm form per floor of the predicted dwell weights."""
+    params = class_solution.VOLUME if params is None else params
+    pl = Planner(dtype=dtype_ctx, max_plans=W.shape[0])
+    pl.load(case, params)
+    _, F_ref = _timed_run(pl, W, None, [Stage("f32acc64", ref_iters)])
+    forms = {"cold_f32": lambda n: (None, [Stage("f32", n)])}
+    for fl in floors:
+        t_warm = warm_start_times(net, pl, W, fl)
+        forms[f"warm_bf16_floor{fl:g}"] = (
+            lambda n, t_warm=t_warm: (t_warm, [Stage("bf16", min(n, warm_bf16_steps))] +
+                                      ([Stage("f32", n)] if n > warm_bf16_steps else [])))
+    out = {}
+    for name, form in forms.items():
+        res = {}
+        curve = []
+        for n in grid:
+            t0, stages = form(n)
+            ms, F = _timed_run(pl, W, t0, stages)
+            worst = float(np.max(F / F_ref - 1.0))
+            curve.append((n, ms, worst))
+        for a in targets:
+            hit = next(((n, ms) for n, ms, w in curve if w <= a), None)
+            res[str(a)] = None if hit is None else {"steps": hit[0], "device_ms": hit[1]}
+        out[name] = dict(time_to_target=res, curve=[{"steps": n, "device_ms": ms, "worst_rel_excess": w}
+                                                    for n, ms, w in curve])
     pl.close()
     return out
 
