@@ -100,6 +100,12 @@ def load_library(path: Optional[str] = None):
     if _lib is not None and path is None:
         return _lib
     p = path or LIB_PATH
+    # PyTorch (when installed) must bring in its HIP runtime before the
+    # library does, so that both share one runtime in this process
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(p):
         raise FileNotFoundError(
             f"{p} is missing: build it with `python -m paper_1904_01567_amd.build`")
@@ -169,6 +175,9 @@ class Planner:
 
     def __init__(self, device: int = 0, dtype: str = "f32", history: int = 10,
                  max_plans: int = 1000, use_torch: bool = True):
+        if use_torch:
+            import torch  # device memory and stream come from PyTorch
+            torch.cuda.set_device(device)
         self.lib = load_library()
         self._ctx = C.c_void_p()
         self._ws = None
@@ -179,9 +188,7 @@ class Planner:
         self.K = self.M = self.G = self.O = 0
         self.P = 0
         if use_torch:
-            import torch  # device memory and stream come from PyTorch
             self._torch = torch
-            torch.cuda.set_device(device)
             self.set_stream(torch.cuda.current_stream(device).cuda_stream)
 
     # -- plumbing --------------------------------------------------------
@@ -398,6 +405,9 @@ class Network:
     """The learned warm start's network on the GPU (gmco_mlp_*)."""
 
     def __init__(self, sizes, max_batch: int = 1024, device: int = 0, use_torch: bool = True):
+        if use_torch:
+            import torch
+            torch.cuda.set_device(device)
         self.lib = load_library()
         self._net = C.c_void_p()
         self.sizes = [int(v) for v in sizes]
