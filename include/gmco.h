@@ -258,16 +258,19 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_r
                        int rounds_per_graph);
 
 /* Autotuner: time the evaluation kernel of this case and batch for each
- * candidate split count of the point range (workgroups per plan tile; up to
- * 32) and keep the fastest.  reps timed launches per candidate on the
- * context stream.  Needs a weight batch.  best_split / best_us may be NULL.
- * The tuned split is used by rounds in which every plan tile of the batch
- * capacity is active; rounds with fewer active plans (stopped plans are
+ * candidate split count of the point range (workgroups per plan tile of 64
+ * plans, or per pair of tiles for the BF16 and FP8 kernels up to 448 padded
+ * dwells; up to 32) and keep the fastest.  reps timed launches per candidate
+ * on the context stream.  Needs a weight batch.  best_split / best_us may be
+ * NULL.  The tuned split belongs to the kernel family of dtype (FP32 operands,
+ * or BF16 / FP8) and is used by its rounds in which every plan tile of the
+ * batch capacity is active; rounds with fewer active plans (stopped plans are
  * compacted out) choose their split on the device to fill the compute units. */
 int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* best_us);
 
-/* Set the split count directly (e.g. from a cache of autotuned shapes); same
- * scope as the autotuner's.  1 <= split <= the autotuner's range. */
+/* Set the split count directly (e.g. from a cache of autotuned shapes) for
+ * both kernel families; otherwise the autotuner's scope.  1 <= split <= the
+ * autotuner's range. */
 int gmco_set_split(gmco_ctx* ctx, int split);
 
 /* t = x^2 of every plan, P x K, FP64 (computed on the device). */

@@ -34,8 +34,13 @@ struct Dims {
   int Md = 0, Mdp = 0;  // DVH points (0: none), padded
   int S_cap = 1;      // split counts up to this fit the partial buffers (autotuning range)
   int S_tuned = 0;    // split set by the caller or the autotuner, 0 = heuristic
+  int S_lp = 1;       // S and S_tuned of the BF16 / FP8 kernels, whose
+  int S_tuned_lp = 0; // workgroups cover lpt tiles each
+  int lpt = 1;
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
-  int grid_cap = 1;   // workgroups (of kPT columns) the partial buffers hold
+  int grid16 = 1;     // largest grid a compacted round launches: FP32 operands,
+  int grid32 = 1;     // BF16 / FP8
+  int grid_cap = 1;   // plan tiles times splits the partial buffers hold
   // split count per active tile count 0..ntiles, for 16-point (FP32 modes)
   // and 32-point (BF16, FP8) evaluation blocks
   std::vector<int> split16, split32;
@@ -140,18 +145,24 @@ Dims make_dims(int M, int K, int Pmax, int n_cu, int Md) {
   d.nblocks = d.Mp / kBM;
   d.Pp = round_up(Pmax, kPT);
   d.ntiles = d.Pp / kPT;
-  d.S = choose_split(d.ntiles, d.nblocks, n_cu, kSplitMax);
-  d.S_cap = std::max(d.S, std::min(kSplitTuneMax, d.nblocks));
+  d.lpt = lp_tiles(d.Kp);
   // compacted rounds choose their split on the device for 1..ntiles active
-  // tiles, with the 16-point (FP32) or 32-point (BF16, FP8) block count
-  d.grid_heur = 1;
+  // tiles, with the 16-point (FP32) or 32-point (BF16, FP8) block count and
+  // workgroups of 1 or lpt tiles
+  d.grid_heur = d.grid16 = d.grid32 = 1;
   d.split16.assign(d.ntiles + 1, 1);
   d.split32.assign(d.ntiles + 1, 1);
   for (int nt = 1; nt <= d.ntiles; ++nt) {
+    const int units = (nt + d.lpt - 1) / d.lpt;
     d.split16[nt] = choose_split(nt, d.nblocks, n_cu, kSplitMax);
-    d.split32[nt] = choose_split(nt, d.Mp / 32, n_cu, kSplitMax);
+    d.split32[nt] = choose_split(units, d.Mp / 32, n_cu, kSplitMax);
     d.grid_heur = std::max(d.grid_heur, nt * std::max(d.split16[nt], d.split32[nt]));
+    d.grid16 = std::max(d.grid16, nt * d.split16[nt]);
+    d.grid32 = std::max(d.grid32, units * d.split32[nt]);
   }
+  d.S = d.split16[d.ntiles];
+  d.S_lp = d.split32[d.ntiles];
+  d.S_cap = std::max(std::max(d.S, d.S_lp), std::min(kSplitTuneMax, d.nblocks));
   d.grid_cap = std::max(d.grid_heur, d.ntiles * d.S_cap);
   return d;
 }
@@ -247,6 +258,9 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.grp = c->at<int>(c->lay.grp);
   a.x = x;
   a.wn = c->at<float>(c->lay.wn);
+  const Dims& d = c->dim;
+  const bool lp = is_low_precision(dtype);
+  const int units = lp ? (d.ntiles + d.lpt - 1) / d.lpt : d.ntiles;
   if (compacted) {
     a.flag = c->at<int>(c->lay.flag);
     a.split_tab = c->at<int>(c->lay.split_tab) + (is_low_precision(dtype) ? c->dim.ntiles + 1 : 0);
@@ -254,7 +268,7 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
     a.rt = c->at<RoundTable>(c->lay.rt);
     a.work = c->at<unsigned long long>(c->lay.work);
     a.P = c->P;
-    a.s_tuned = c->dim.S_tuned;
+    a.s_tuned = lp ? d.S_tuned_lp : d.S_tuned;
   }
   a.Gpart = c->at<float>(c->lay.Gpart);
   a.Fpart = c->at<double>(c->lay.Fpart);
@@ -262,9 +276,10 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.Kp = c->dim.Kp;
   a.Pp = c->dim.Pp;
   a.nblocks = c->dim.nblocks;
-  a.S = c->dim.S;
-  a.ntiles = c->dim.ntiles;
-  a.grid = compacted ? std::max(c->dim.grid_heur, c->dim.ntiles * c->dim.S_tuned) : a.S * a.ntiles;
+  a.S = lp ? d.S_lp : d.S;
+  a.ntiles = d.ntiles;
+  a.grid = compacted ? std::max(lp ? d.grid32 : d.grid16, units * (lp ? d.S_tuned_lp : d.S_tuned))
+                     : a.S * units;
   a.gt = c->gt;
   return a;
 }
@@ -611,7 +626,7 @@ int gmco_evaluate(gmco_ctx* c, const double* x, double* F, double* g) {
   GMCO_HIP(c, launch_x_to_device(c->at<double>(L.xst), P, c->dim.Pp, K, c->dim.Kp, c->at<float>(L.xe), c->stream));
   EvalArgs a = eval_args(c, c->at<float>(L.xe), false, c->dtype);
   GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
-  GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, c->at<float>(L.xe), c->dim.S, P, c->dim.Pp, K,
+  GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, c->at<float>(L.xe), a.S, P, c->dim.Pp, K,
                                  c->dim.Kp, c->at<double>(L.Fst), c->at<double>(L.gst), c->stream));
   GMCO_HIP(c, hipMemcpyAsync(F, c->at<void>(L.Fst), (size_t)P * 8, hipMemcpyDeviceToHost, c->stream));
   GMCO_HIP(c, hipMemcpyAsync(g, c->at<void>(L.gst), (size_t)P * K * 8, hipMemcpyDeviceToHost, c->stream));
@@ -839,15 +854,16 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
   if (!dtype_available(c->dtype, dtype)) return fail(c, GMCO_EINVAL, "dtype not available");
   GMCO_HIP(c, hipSetDevice(c->device));
   Dims& d = c->dim;
+  int& S_dense = is_low_precision(dtype) ? d.S_lp : d.S;  // the split this dtype's kernel uses
   std::vector<int> cand;
-  for (int s : {d.S, 4, 8, 12, 16, 20, 24, 28, 32})
+  for (int s : {S_dense, 4, 8, 12, 16, 20, 24, 28, 32})
     if (s >= 1 && s <= d.S_cap && s <= d.nblocks && std::find(cand.begin(), cand.end(), s) == cand.end())
       cand.push_back(s);
-  const int orig = d.S;
+  const int orig = S_dense;
   int best = orig;
   float best_t = 1e30f;
   for (int s : cand) {
-    d.S = s;
+    S_dense = s;
     EvalArgs a = eval_args(c, c->at<float>(c->lay.xt), false, dtype);
     GMCO_HIP(c, launch_eval(a, dtype, c->stream));  // warm-up
     GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
@@ -862,8 +878,8 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
       best = s;
     }
   }
-  d.S = best;
-  d.S_tuned = best;
+  S_dense = best;
+  (is_low_precision(dtype) ? d.S_tuned_lp : d.S_tuned) = best;
   if (best_split) *best_split = best;
   if (best_us) *best_us = best_t;
   return GMCO_OK;
@@ -873,8 +889,8 @@ int gmco_set_split(gmco_ctx* c, int split) {
   if (!c) return GMCO_EINVAL;
   if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
   if (split < 1 || split > c->dim.S_cap || split > c->dim.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
-  c->dim.S = split;
-  c->dim.S_tuned = split;
+  c->dim.S = c->dim.S_lp = split;
+  c->dim.S_tuned = c->dim.S_tuned_lp = split;
   return GMCO_OK;
 }
 

@@ -11,7 +11,13 @@ namespace gmco {
 
 constexpr int kGmax = GMCO_MAX_GROUPS;
 constexpr int kBM = 16;   // dose points per inner block of the evaluation kernel
-constexpr int kPT = 64;   // plans per workgroup tile of the evaluation kernel
+constexpr int kPT = 64;   // plans per tile of the evaluation (one FP32 workgroup)
+// Plan tiles per BF16 / FP8 evaluation workgroup.  One (16 plans per
+// wavefront) lets two workgroups share a compute unit up to Kp = 384, which
+// hides more latency than two tiles (32 plans per wavefront, one workgroup)
+// save in loads; above that only one workgroup fits either way, and two tiles
+// are used where their registers fit without spilling (Kp = 416).
+__host__ __device__ constexpr int lp_tiles(int Kp) { return Kp == 416 ? 2 : 1; }
 constexpr int kKAlign = 32;
 constexpr int kMAlign = 32;  // points: a multiple of every kernel's block
 constexpr int kSplitMax = 256;  // largest split-M count the heuristic picks
@@ -69,11 +75,14 @@ struct EvalArgs {
   const int* grp;         // [Mp] structure index, kGmax for padding
   const float* x;         // [Pp][Kp] points to evaluate (dwell weights)
   const float* wn;        // [Pp][kGmax] w_j / N_j
+  // A workgroup covers T consecutive tiles of kPT columns (T = 1 for FP32
+  // operands, lp_tiles(Kp) for BF16 / FP8); the grid of a round is S times
+  // ceil(ntiles / T) workgroups.
   // Compacted rounds (flag != NULL): every workgroup counts the running
   // plans (flag[p] = 1) in plan order, takes the round's tile count
   // ntiles = ceil(nact / kPT) and split count split_tab[ntiles] (s_tuned
-  // instead when every tile of the capacity is active), and maps its kPT
-  // columns to the plans of compact ranks j0 .. j0 + kPT - 1.  Split-0
+  // instead when every tile of the capacity is active), and maps its T kPT
+  // columns to the plans of compact ranks j0 .. j0 + T kPT - 1.  Split-0
   // workgroups record each plan's rank in slot; workgroup 0 writes the
   // round's shape to rt and adds nact to work.  The partials are then
   // [S][ntiles * kPT][Kp] by rank.  flag == NULL: every plan, column = plan,
@@ -92,7 +101,7 @@ struct EvalArgs {
   int nblocks;            // Mp / kBM (16-point blocks)
   int S;                  // M splits (uncompacted form)
   int ntiles;             // Pp / kPT (uncompacted form)
-  int grid;               // workgroups launched; those past S * ntiles exit
+  int grid;               // workgroups launched; those past the round's grid exit
   GroupTable gt;
 };
 

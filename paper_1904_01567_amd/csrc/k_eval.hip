@@ -54,26 +54,30 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
 
 // Resolves the evaluation's shape (split count S, tile count, row stride of
 // the partial buffers), this workgroup's (split, first compact column j0) and
-// the plan behind each of its kPT columns (-1: empty), and stages the
+// the plan behind each of its TPW * kPT columns (-1: empty), and stages the
 // columns' structure weights.  In a compacted round every workgroup ranks
 // the running plans itself (a block-wide scan of the flags), so no separate
 // launch is needed.  Returns false, for the whole workgroup, when the grid
-// is larger than this round's S * ntiles.
-template <int NT>
+// is larger than this round's S * ceil(ntiles / TPW).  Columns at or past
+// `stride` (the second tile of the last workgroup when ntiles is odd) are
+// empty and have no partials.
+template <int NT, int TPW = 1>
 __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, float* sW, int& s,
                                   int& S, int& stride, int& j0) {
+  constexpr int NCOL = TPW * kPT;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  int tile;
+  int unit;
   if (a.flag == nullptr) {
     S = a.S;
     stride = a.Pp;
-    if ((int)blockIdx.x >= S * a.ntiles) return false;
-    split_tile(blockIdx.x, S, a.ntiles, s, tile);
-    j0 = tile * kPT;
-    if (tid < kPT) sPlan[tid] = j0 + tid;
+    const int units = (a.ntiles + TPW - 1) / TPW;
+    if ((int)blockIdx.x >= S * units) return false;
+    split_tile(blockIdx.x, S, units, s, unit);
+    j0 = unit * NCOL;
+    for (int i = tid; i < NCOL; i += NT) sPlan[i] = j0 + i < a.Pp ? j0 + i : -1;
   } else {
-    if (tid < kPT) sPlan[tid] = -1;
+    for (int i = tid; i < NCOL; i += NT) sPlan[i] = -1;
     const int per = (a.P + NT - 1) / NT;
     const int b = tid * per;
     const int e = min(b + per, a.P);
@@ -107,13 +111,14 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
       if (a.work != nullptr) *a.work += (unsigned long long)nact;
       if (a.work2 != nullptr) *a.work2 += (unsigned long long)nact;
     }
-    if ((int)blockIdx.x >= S * ntiles) return false;
-    split_tile(blockIdx.x, S, ntiles, s, tile);
-    j0 = tile * kPT;
+    const int units = (ntiles + TPW - 1) / TPW;
+    if ((int)blockIdx.x >= S * units) return false;
+    split_tile(blockIdx.x, S, units, s, unit);
+    j0 = unit * NCOL;
     int r = base + v - cnt;
     for (int p = b; p < e; ++p) {
       if (a.flag[p]) {
-        if (r >= j0 && r < j0 + kPT) {
+        if (r >= j0 && r < j0 + NCOL) {
           sPlan[r - j0] = p;
           if (s == 0) a.slot[p] = r;
         }
@@ -122,7 +127,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     }
   }
   __syncthreads();
-  for (int i = tid; i < kPT * kGmax; i += NT) {
+  for (int i = tid; i < NCOL * kGmax; i += NT) {
     const int pl = sPlan[i / kGmax];
     sW[i] = pl >= 0 ? a.wn[(size_t)pl * kGmax + (i % kGmax)] : 0.f;
   }
@@ -504,14 +509,30 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16.  Lane l
-// (q = l / 16, n = l % 16) supplies A[n][8q .. 8q+7] and B[8q .. 8q+7][n];
-// accumulator register r holds C[4q + r][n].  Blocks of 32 points: the dose
+// Low-precision operands, FP32 accumulation.
+//   BF16: both products in v_mfma_f32_16x16x32_bf16.
+//   FP8 : the dose product in e4m3 (v_mfma_f32_16x16x32_fp8_fp8): D is stored
+//         as D_il / s_l with one scale per dwell column
+//         (s_l = max_i D_il / 224), the dwell times enter as t_l s_l / u_p
+//         with one scale per plan (u_p = max_l t_l s_l / 224), and
+//         d = u_p * sum.  The back-projection runs in BF16 on the BF16
+//         transposed copy of D.  Both conversions use the hardware's own FP8
+//         encoding, so the format convention never enters the arithmetic.
+// Lane l (q = l / 16, n = l % 16) supplies A[n][8q .. 8q+7] and
+// B[8q .. 8q+7][n] (eight 2- or 1-byte elements); accumulator register r
+// holds C[4q + r][n].
+// A workgroup evaluates lp_tiles(Kp) plan tiles: 128 plans up to Kp = 448,
+// where each wave holds the dwell times and gradient accumulators of 32
+// plans as two 16-plan halves, so that every operand of D read from LDS
+// feeds two matrix ops and every block of D staged in LDS serves 128 plans
+// (64 plans, 16 per wave, above).  Blocks of 32 points: the dose
 // product runs two 16-point row tiles, after which each lane holds the
 // penalty derivative of points {4q..4q+3} and {16+4q..16+4q+3} of its plan,
-// exactly the 8 contraction slots it supplies to the back-projection; the
-// back-projection's A operand (D transposed) is read in that same point
-// order from a dwell-major copy of the tile.
+// exactly the 8 contraction slots it supplies to the back-projection, whose
+// A operand (D transposed) is read in that point order from a dwell-major
+// tile.  The BF16 kernel writes that tile itself from the row-major block it
+// stages (two points per 32-bit word), so D is read from memory once; the
+// FP8 kernel loads it from the BF16 transposed copy.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
@@ -522,164 +543,6 @@ __device__ inline f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int KP>
-__global__ __launch_bounds__(256, 1) void k_eval_bf16(EvalArgs a) {
-  constexpr int BMP = 32;              // points per block
-  constexpr int DS = KP + 8;           // D tile row stride (elements): conflict-free b128 reads
-  constexpr int TS = BMP + 4;          // transposed tile row stride: conflict-free b64 reads
-  constexpr int NK32 = KP / 32;        // k-steps of the dose product
-  constexpr int NK16 = KP / 16;        // 16-dwell tiles of the back-projection
-  constexpr int NCH = BMP * KP / 8;    // 16-byte chunks per tile (both tiles)
-  constexpr int NPF = (NCH + 255) / 256;
-
-  __shared__ __attribute__((aligned(16))) __bf16 sD[BMP * DS];
-  __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
-  __shared__ float sW[kPT * kGmax];
-  __shared__ int sPlan[kPT];
-  __shared__ int sScan[4];
-  __shared__ float4 sP[kGmax + 1];
-  __shared__ int sG[BMP];
-
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int lane = tid & 63;
-  const int q = lane >> 4;
-  const int n = lane & 15;
-  int s, S, stride, j0;
-  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
-#pragma unroll
-  for (int j = 0; j <= kGmax; ++j)
-    if (tid == j) sP[j] = a.gt.prm[j];
-
-  const int col = wave * 16 + n;
-  const int plan = sPlan[col];
-  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
-  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
-  // B operand of the dose product: t = x^2 of plan n at dwells 32 k + 8 q + e
-  bf8v tb[NK32];
-#pragma unroll
-  for (int k = 0; k < NK32; ++k) {
-    const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
-    const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
-    tb[k][0] = (__bf16)(pv ? x0.x * x0.x : 0.f);
-    tb[k][1] = (__bf16)(pv ? x0.y * x0.y : 0.f);
-    tb[k][2] = (__bf16)(pv ? x0.z * x0.z : 0.f);
-    tb[k][3] = (__bf16)(pv ? x0.w * x0.w : 0.f);
-    tb[k][4] = (__bf16)(pv ? x1.x * x1.x : 0.f);
-    tb[k][5] = (__bf16)(pv ? x1.y * x1.y : 0.f);
-    tb[k][6] = (__bf16)(pv ? x1.z * x1.z : 0.f);
-    tb[k][7] = (__bf16)(pv ? x1.w * x1.w : 0.f);
-  }
-  f4v gacc[NK16];
-#pragma unroll
-  for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
-  double facc = 0.0;
-
-  const int nb = a.Mp / BMP;
-  const int b_begin = (int)(((long long)s * nb) / S);
-  const int b_end = (int)(((long long)(s + 1) * nb) / S);
-  const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
-  const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
-
-  u4v pd[NPF], pt[NPF];
-  int gpre = 0;
-#define GMCO_PF16(blk)                                                          \
-  {                                                                             \
-    const u4v* srcd = Dg + (size_t)(blk) * NCH;                                 \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                           \
-      const int c = tid + 256 * i;                                              \
-      if (NCH % 256 == 0 || c < NCH) {                                          \
-        pd[i] = srcd[c];                                                        \
-        const int l = c >> 2, part = c & 3;                                    \
-        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp +          \
-                                                (size_t)(blk) * BMP + part * 8); \
-      }                                                                         \
-    }                                                                           \
-    if (tid < BMP) gpre = a.grp[(blk) * BMP + tid];                             \
-  }
-  if (b_begin < b_end) GMCO_PF16(b_begin);
-
-  for (int b = b_begin; b < b_end; ++b) {
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NPF; ++i) {
-      const int c = tid + 256 * i;
-      if (NCH % 256 == 0 || c < NCH) {
-        const int row = c / (KP / 8), c8 = c - row * (KP / 8);
-        *reinterpret_cast<u4v*>(&sD[row * DS + 8 * c8]) = pd[i];
-        const int l = c >> 2, part = c & 3;
-        u2v* dst = reinterpret_cast<u2v*>(&sT[l * TS + part * 8]);
-        dst[0] = u2v{pt[i][0], pt[i][1]};
-        dst[1] = u2v{pt[i][2], pt[i][3]};
-      }
-    }
-    if (tid < BMP) sG[tid] = gpre;
-    __syncthreads();
-    {
-      const int bn = (b + 1 < b_end) ? b + 1 : b;
-      GMCO_PF16(bn);
-    }
-
-    // ---- dose product for the two 16-point row tiles ----
-    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-#pragma unroll
-    for (int k = 0; k < NK32; ++k) {
-      const bf8v a0 = *reinterpret_cast<const bf8v*>(&sD[n * DS + 32 * k + 8 * q]);
-      const bf8v a1 = *reinterpret_cast<const bf8v*>(&sD[(16 + n) * DS + 32 * k + 8 * q]);
-      acc0 = mfma_bf16(a0, tb[k], acc0);
-      acc1 = mfma_bf16(a1, tb[k], acc1);
-    }
-    // ---- penalty epilogue ----
-    bf8v phi;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float d = e < 4 ? acc0[e] : acc1[e - 4];
-      const int pt_ = e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4);
-      const int gi = sG[pt_];
-      const float4 pr = sP[gi];
-      const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-      float kap = 0.f, dev = 0.f;
-      if (d < pr.y) {
-        dev = d - pr.y;
-        kap = pr.x * dev;
-      } else if (d > pr.z) {
-        dev = d - pr.z;
-        kap = pr.w * dev;
-      }
-      facc += (double)(w * (kap * dev));
-      phi[e] = (__bf16)(w * kap);
-    }
-    // ---- back-projection over the 32 points ----
-#pragma unroll
-    for (int k = 0; k < NK16; ++k) {
-      const bf4v lo = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 4 * q]);
-      const bf4v hi = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 16 + 4 * q]);
-      const bf8v av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      gacc[k] = mfma_bf16(av, phi, gacc[k]);
-    }
-  }
-#undef GMCO_PF16
-
-  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
-#pragma unroll
-  for (int k = 0; k < NK16; ++k) {
-    *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
-        make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
-  }
-  facc += __shfl_xor(facc, 16);
-  facc += __shfl_xor(facc, 32);
-  if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
-}
-
-// ---------------------------------------------------------------------------
-// FP8 dose product (e4m3, v_mfma_f32_16x16x32_fp8_fp8, same lane layout as the
-// BF16 op with 8 one-byte elements per lane): D is stored as D_il / s_l with
-// one scale per dwell column (s_l = max_i D_il / 224), the dwell times enter
-// as t_l s_l / u_p with one scale per plan (u_p = max_l t_l s_l / 224), and
-// d = u_p * sum.  The back-projection runs in BF16 on the BF16 transposed
-// copy of D, as in the BF16 kernel.  Both conversions use the hardware's own
-// FP8 encoding, so the format convention never enters the arithmetic.
-// ---------------------------------------------------------------------------
 __device__ inline f4v mfma_fp8(long a, long b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
 }
@@ -689,22 +552,57 @@ __device__ inline unsigned pack_fp8x4(float a, float b, float c, float d) {
   return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
 }
 
-template <int KP>
-__global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
-  constexpr int BMP = 32;
-  constexpr int DS = KP + 8;           // FP8 tile row stride (bytes): conflict-free b64 reads
-  constexpr int TS = BMP + 4;          // BF16 transposed tile row stride (elements)
-  constexpr int NK32 = KP / 32;
-  constexpr int NK16 = KP / 16;
-  constexpr int NCH8 = BMP * KP / 16;  // 16-byte chunks of the FP8 tile
-  constexpr int NCH = BMP * KP / 8;    // 16-byte chunks of the BF16 transposed tile
-  constexpr int NPF8 = (NCH8 + 255) / 256;
-  constexpr int NPF = (NCH + 255) / 256;
+// Eq. 1 at dose d for the row pr = (w_min, D_min, D_max, w_max), without
+// branches: with lo = min(d - D_min, 0) and hi = max(d - D_max, 0) (at most
+// one is nonzero since D_min <= D_max) the bracket of eq. 2 is
+// kappa = w_min lo + w_max hi and the penalty kappa (lo + hi).  Adds w times
+// the penalty to f and returns phi = w kappa in BF16.
+__device__ inline __bf16 penalty_lp(float d, float4 pr, float w, double& f) {
+  const float lo = fminf(d - pr.y, 0.f);
+  const float hi = fmaxf(d - pr.z, 0.f);
+  const float kap = pr.x * lo + pr.w * hi;
+  f += (double)(w * (kap * (lo + hi)));
+  return (__bf16)(w * kap);
+}
 
-  __shared__ __attribute__((aligned(16))) unsigned char sD[BMP * DS];
+template <bool FP8>
+struct LpOp;
+template <>
+struct LpOp<false> {
+  typedef bf8v type;
+  static __device__ inline f4v mma(bf8v a, bf8v b, f4v c) { return mfma_bf16(a, b, c); }
+};
+template <>
+struct LpOp<true> {
+  typedef long type;
+  static __device__ inline f4v mma(long a, long b, f4v c) { return mfma_fp8(a, b, c); }
+};
+
+template <int KP, bool FP8>
+__device__ inline void eval_lp(const EvalArgs& a) {
+  typedef typename LpOp<FP8>::type op_t;
+  constexpr int BMP = 32;              // points per block
+  constexpr int DS = KP + 8;           // D tile row stride (elements): conflict-free reads
+  constexpr int TS = BMP + 4;          // transposed tile row stride: conflict-free b64 reads
+  constexpr int NK32 = KP / 32;        // k-steps of the dose product
+  constexpr int NK16 = KP / 16;        // 16-dwell tiles of the back-projection
+  constexpr int NH = lp_tiles(KP);    // 16-plan halves per wavefront
+  constexpr int NCOL = NH * kPT;
+  // BF16 staging: (row pair, 8-dwell chunk) tasks, row pair fastest
+  constexpr int NC8 = KP / 8;
+  constexpr int NTASK = (BMP / 2) * NC8;
+  constexpr int NPT = FP8 ? 1 : (NTASK + 255) / 256;
+  // FP8 staging: 16-byte chunks of the FP8 tile and of the BF16 transposed tile
+  constexpr int NCH8 = BMP * KP / 16;
+  constexpr int NCH = BMP * KP / 8;
+  constexpr int NPF8 = FP8 ? (NCH8 + 255) / 256 : 1;
+  constexpr int NPF = FP8 ? (NCH + 255) / 256 : 1;
+  static_assert(NC8 % 4 == 0, "a wavefront's staging tasks span whole chunk groups");
+
+  __shared__ __attribute__((aligned(16))) unsigned char sD[BMP * DS * (FP8 ? 1 : 2)];
   __shared__ __attribute__((aligned(16))) __bf16 sT[KP * TS];
-  __shared__ float sW[kPT * kGmax];
-  __shared__ int sPlan[kPT];
+  __shared__ float sW[NCOL * kGmax];
+  __shared__ int sPlan[NCOL];
   __shared__ int sScan[4];
   __shared__ float4 sP[kGmax + 1];
   __shared__ int sG[BMP];
@@ -714,44 +612,74 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int n = lane & 15;
-  int s, S, stride, j0;
-  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (tid == 0) {  // constant indices: the table is read straight from the kernel arguments
 #pragma unroll
-  for (int j = 0; j <= kGmax; ++j)
-    if (tid == j) sP[j] = a.gt.prm[j];
+    for (int j = 0; j <= kGmax; ++j) sP[j] = a.gt.prm[j];
+  }
+  int s, S, stride, j0;  // (tile_setup ends with a barrier)
+  if (!tile_setup<256, NH>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
 
-  const int col = wave * 16 + n;
-  const int plan = sPlan[col];
-  const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
-  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
-  // scaled dwell times t_l s_l, their per-plan maximum, then FP8 and BF16 fragments
-  float ts[NK32][8];
-  float tmax = 0.f;
+  // B operands of the dose product, t = x^2 at dwells 32 k + 8 q + e, for
+  // the plans of columns 16 (NH wave + h) + n (an empty column evaluates t = 0
+  // with zero weights)
+  op_t tb[NH][NK32];
+  float u[NH];
 #pragma unroll
-  for (int k = 0; k < NK32; ++k) {
+  for (int h = 0; h < NH; ++h) {
+    u[h] = 1.f;
+    const int plan = sPlan[16 * (NH * wave + h) + n];
+    const bool pv = plan >= 0;
+    const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
+    if constexpr (!FP8) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int l = 32 * k + 8 * q + e;
-      const float xv = xrow[l];
-      ts[k][e] = pv ? xv * xv * a.colscale[l] : 0.f;
-      tmax = fmaxf(tmax, ts[k][e]);
+      for (int k = 0; k < NK32; ++k) {
+        const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
+        const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
+        tb[h][k][0] = (__bf16)(pv ? x0.x * x0.x : 0.f);
+        tb[h][k][1] = (__bf16)(pv ? x0.y * x0.y : 0.f);
+        tb[h][k][2] = (__bf16)(pv ? x0.z * x0.z : 0.f);
+        tb[h][k][3] = (__bf16)(pv ? x0.w * x0.w : 0.f);
+        tb[h][k][4] = (__bf16)(pv ? x1.x * x1.x : 0.f);
+        tb[h][k][5] = (__bf16)(pv ? x1.y * x1.y : 0.f);
+        tb[h][k][6] = (__bf16)(pv ? x1.z * x1.z : 0.f);
+        tb[h][k][7] = (__bf16)(pv ? x1.w * x1.w : 0.f);
+      }
+    } else {
+      // scaled dwell times t_l s_l, their per-plan maximum, then FP8 fragments
+      float ts[NK32][8];
+      float tmax = 0.f;
+#pragma unroll
+      for (int k = 0; k < NK32; ++k) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int l = 32 * k + 8 * q + e;
+          const float xv = xrow[l];
+          ts[k][e] = pv ? xv * xv * a.colscale[l] : 0.f;
+          tmax = fmaxf(tmax, ts[k][e]);
+        }
+      }
+      tmax = fmaxf(tmax, __shfl_xor(tmax, 16));
+      tmax = fmaxf(tmax, __shfl_xor(tmax, 32));
+      u[h] = tmax > 0.f ? tmax / 224.f : 1.f;
+      const float inv_u = 1.f / u[h];
+#pragma unroll
+      for (int k = 0; k < NK32; ++k) {
+        const unsigned lo = pack_fp8x4(ts[k][0] * inv_u, ts[k][1] * inv_u, ts[k][2] * inv_u,
+                                       ts[k][3] * inv_u);
+        const unsigned hi = pack_fp8x4(ts[k][4] * inv_u, ts[k][5] * inv_u, ts[k][6] * inv_u,
+                                       ts[k][7] * inv_u);
+        tb[h][k] = (long)(((unsigned long)hi << 32) | lo);
+      }
     }
   }
-  tmax = fmaxf(tmax, __shfl_xor(tmax, 16));
-  tmax = fmaxf(tmax, __shfl_xor(tmax, 32));
-  const float u = tmax > 0.f ? tmax / 224.f : 1.f;
-  const float inv_u = 1.f / u;
-  long tb[NK32];
+  f4v gacc[NH][NK16];
 #pragma unroll
-  for (int k = 0; k < NK32; ++k) {
-    const unsigned lo = pack_fp8x4(ts[k][0] * inv_u, ts[k][1] * inv_u, ts[k][2] * inv_u, ts[k][3] * inv_u);
-    const unsigned hi = pack_fp8x4(ts[k][4] * inv_u, ts[k][5] * inv_u, ts[k][6] * inv_u, ts[k][7] * inv_u);
-    tb[k] = (long)(((unsigned long)hi << 32) | lo);
-  }
-  f4v gacc[NK16];
+  for (int h = 0; h < NH; ++h)
 #pragma unroll
-  for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
-  double facc = 0.0;
+    for (int k = 0; k < NK16; ++k) gacc[h][k] = f4v{0.f, 0.f, 0.f, 0.f};
+  double facc[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) facc[h] = 0.0;
 
   const int nb = a.Mp / BMP;
   const int b_begin = (int)(((long long)s * nb) / S);
@@ -759,102 +687,184 @@ __global__ __launch_bounds__(256, 1) void k_eval_fp8(EvalArgs a) {
   const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
   const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
 
-  u4v pd[NPF8], pt[NPF];
+  u4v p0[NPT], p1[NPT];    // BF16: rows 2 rp and 2 rp + 1 of chunk c8
+  u4v pd[NPF8], pt[NPF];   // FP8: tile chunks, transposed-tile chunks
   int gpre = 0;
-#define GMCO_PF8(blk)                                                           \
-  {                                                                             \
-    const u4v* srcd = Dg + (size_t)(blk) * NCH8;                                \
-    _Pragma("unroll") for (int i = 0; i < NPF8; ++i) {                          \
-      const int c = tid + 256 * i;                                              \
-      if (NCH8 % 256 == 0 || c < NCH8) pd[i] = srcd[c];                         \
-    }                                                                           \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                           \
-      const int c = tid + 256 * i;                                              \
-      if (NCH % 256 == 0 || c < NCH) {                                          \
-        const int l = c >> 2, part = c & 3;                                     \
-        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp +          \
-                                              (size_t)(blk) * BMP + part * 8);  \
-      }                                                                         \
-    }                                                                           \
-    if (tid < BMP) gpre = a.grp[(blk) * BMP + tid];                             \
-  }
-  if (b_begin < b_end) GMCO_PF8(b_begin);
+  auto prefetch = [&](int blk) {
+    // threads past the last chunk load the last one again (every register
+    // is defined on every path) and do not store it
+    if constexpr (!FP8) {
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int c = min(tid + 256 * i, NTASK - 1);
+        const int rp = c & 15, c8 = c >> 4;
+        const u4v* src = Dg + ((size_t)blk * BMP + 2 * rp) * NC8 + c8;
+        p0[i] = src[0];
+        p1[i] = src[NC8];
+      }
+    } else {
+      const u4v* srcd = Dg + (size_t)blk * NCH8;
+#pragma unroll
+      for (int i = 0; i < NPF8; ++i) pd[i] = srcd[min(tid + 256 * i, NCH8 - 1)];
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) {
+        const int c = min(tid + 256 * i, NCH - 1);
+        const int l = c >> 2, part = c & 3;
+        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp + (size_t)blk * BMP +
+                                              part * 8);
+      }
+    }
+    if (tid < BMP) gpre = a.grp[blk * BMP + tid];
+  };
+  if (b_begin < b_end) prefetch(b_begin);
 
   for (int b = b_begin; b < b_end; ++b) {
     __syncthreads();
+    if constexpr (!FP8) {
+      __bf16* sD16 = reinterpret_cast<__bf16*>(sD);
+      unsigned* sT32 = reinterpret_cast<unsigned*>(sT);
 #pragma unroll
-    for (int i = 0; i < NPF8; ++i) {
-      const int c = tid + 256 * i;
-      if (NCH8 % 256 == 0 || c < NCH8) {
-        const int row = c / (KP / 16), c16 = c - row * (KP / 16);
-        u2v* dst = reinterpret_cast<u2v*>(&sD[row * DS + 16 * c16]);
-        dst[0] = u2v{pd[i][0], pd[i][1]};
-        dst[1] = u2v{pd[i][2], pd[i][3]};
+      for (int i = 0; i < NPT; ++i) {
+        const int c = tid + 256 * i;
+        if (NTASK % 256 == 0 || c < NTASK) {
+          const int rp = c & 15, c8 = c >> 4;
+          *reinterpret_cast<u4v*>(&sD16[(2 * rp) * DS + 8 * c8]) = p0[i];
+          *reinterpret_cast<u4v*>(&sD16[(2 * rp + 1) * DS + 8 * c8]) = p1[i];
+          // word (dwell 8 c8 + e, points 2 rp .. 2 rp + 1) of the transposed tile
+          unsigned* dst = sT32 + (8 * c8) * (TS / 2) + rp;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            // low halves of both rows, then high halves (byte selects of v_perm)
+            dst[(2 * w) * (TS / 2)] = __builtin_amdgcn_perm(p1[i][w], p0[i][w], 0x05040100u);
+            dst[(2 * w + 1) * (TS / 2)] = __builtin_amdgcn_perm(p1[i][w], p0[i][w], 0x07060302u);
+          }
+        }
       }
-    }
+    } else {
 #pragma unroll
-    for (int i = 0; i < NPF; ++i) {
-      const int c = tid + 256 * i;
-      if (NCH % 256 == 0 || c < NCH) {
-        const int l = c >> 2, part = c & 3;
-        u2v* dst = reinterpret_cast<u2v*>(&sT[l * TS + part * 8]);
-        dst[0] = u2v{pt[i][0], pt[i][1]};
-        dst[1] = u2v{pt[i][2], pt[i][3]};
+      for (int i = 0; i < NPF8; ++i) {
+        const int c = tid + 256 * i;
+        if (NCH8 % 256 == 0 || c < NCH8) {
+          const int row = c / (KP / 16), c16 = c - row * (KP / 16);
+          u2v* dst = reinterpret_cast<u2v*>(&sD[row * DS + 16 * c16]);
+          dst[0] = u2v{pd[i][0], pd[i][1]};
+          dst[1] = u2v{pd[i][2], pd[i][3]};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) {
+        const int c = tid + 256 * i;
+        if (NCH % 256 == 0 || c < NCH) {
+          const int l = c >> 2, part = c & 3;
+          u2v* dst = reinterpret_cast<u2v*>(&sT[l * TS + part * 8]);
+          dst[0] = u2v{pt[i][0], pt[i][1]};
+          dst[1] = u2v{pt[i][2], pt[i][3]};
+        }
       }
     }
     if (tid < BMP) sG[tid] = gpre;
     __syncthreads();
-    {
-      const int bn = (b + 1 < b_end) ? b + 1 : b;
-      GMCO_PF8(bn);
-    }
+    prefetch((b + 1 < b_end) ? b + 1 : b);
 
-    f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    // ---- dose product for the two 16-point row tiles and both plan halves ----
+    f4v acc[NH][2];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) acc[h][0] = acc[h][1] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < NK32; ++k) {
-      const long a0 = *reinterpret_cast<const long*>(&sD[n * DS + 32 * k + 8 * q]);
-      const long a1 = *reinterpret_cast<const long*>(&sD[(16 + n) * DS + 32 * k + 8 * q]);
-      acc0 = mfma_fp8(a0, tb[k], acc0);
-      acc1 = mfma_fp8(a1, tb[k], acc1);
-    }
-    bf8v phi;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float d = u * (e < 4 ? acc0[e] : acc1[e - 4]);
-      const int pt_ = e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4);
-      const int gi = sG[pt_];
-      const float4 pr = sP[gi];
-      const float w = (gi < kGmax) ? sW[(wave * 16 + n) * kGmax + gi] : 0.f;
-      float kap = 0.f, dev = 0.f;
-      if (d < pr.y) {
-        dev = d - pr.y;
-        kap = pr.x * dev;
-      } else if (d > pr.z) {
-        dev = d - pr.z;
-        kap = pr.w * dev;
+      op_t a0, a1;
+      if constexpr (!FP8) {
+        const __bf16* sD16 = reinterpret_cast<const __bf16*>(sD);
+        a0 = *reinterpret_cast<const bf8v*>(&sD16[n * DS + 32 * k + 8 * q]);
+        a1 = *reinterpret_cast<const bf8v*>(&sD16[(16 + n) * DS + 32 * k + 8 * q]);
+      } else {
+        a0 = *reinterpret_cast<const long*>(&sD[n * DS + 32 * k + 8 * q]);
+        a1 = *reinterpret_cast<const long*>(&sD[(16 + n) * DS + 32 * k + 8 * q]);
       }
-      facc += (double)(w * (kap * dev));
-      phi[e] = (__bf16)(w * kap);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        acc[h][0] = LpOp<FP8>::mma(a0, tb[h][k], acc[h][0]);
+        acc[h][1] = LpOp<FP8>::mma(a1, tb[h][k], acc[h][1]);
+      }
     }
+    // ---- penalty epilogue ----
+    // The points are stored grouped by structure, so most blocks hold a
+    // single structure: then the eq. 1 row and the weight w_j / N_j are the
+    // same for all points of the block and are read once.
+    bf8v phi[NH];
+    const int g0 = sG[0];
+    if (__all(sG[lane & (BMP - 1)] == g0)) {
+      const float4 pr = sP[g0];
+      float w[NH];
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+        w[h] = g0 < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + g0] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
+          if constexpr (FP8) d *= u[h];
+          phi[h][e] = penalty_lp(d, pr, w[h], facc[h]);
+        }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gi = sG[e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4)];
+        const float4 pr = sP[gi];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
+          if constexpr (FP8) d *= u[h];
+          const float w = gi < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + gi] : 0.f;
+          phi[h][e] = penalty_lp(d, pr, w, facc[h]);
+        }
+      }
+    }
+    // ---- back-projection over the 32 points ----
 #pragma unroll
     for (int k = 0; k < NK16; ++k) {
       const bf4v lo = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 4 * q]);
       const bf4v hi = *reinterpret_cast<const bf4v*>(&sT[(16 * k + n) * TS + 16 + 4 * q]);
       const bf8v av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      gacc[k] = mfma_bf16(av, phi, gacc[k]);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) gacc[h][k] = mfma_bf16(av, phi[h], gacc[h][k]);
     }
   }
-#undef GMCO_PF8
 
-  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
 #pragma unroll
-  for (int k = 0; k < NK16; ++k) {
-    *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
-        make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  for (int h = 0; h < NH; ++h) {
+    const int col = 16 * (NH * wave + h) + n;
+    double f = facc[h];
+    f += __shfl_xor(f, 16);
+    f += __shfl_xor(f, 32);
+    if (j0 + col - n < stride) {  // the same for the whole wavefront
+      float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
+#pragma unroll
+      for (int k = 0; k < NK16; ++k) {
+        *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
+            make_float4(gacc[h][k][0], gacc[h][k][1], gacc[h][k][2], gacc[h][k][3]);
+      }
+      if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = f;
+    }
   }
-  facc += __shfl_xor(facc, 16);
-  facc += __shfl_xor(facc, 32);
-  if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
+}
+
+// two wavefronts per SIMD (two workgroups per compute unit) while one tile
+// per workgroup keeps the registers within half the file
+template <int KP>
+constexpr int lp_waves() {
+  return (lp_tiles(KP) == 1 && KP <= 384) ? 2 : 1;
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, lp_waves<KP>()) void k_eval_bf16(EvalArgs a) {
+  eval_lp<KP, false>(a);
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, lp_waves<KP>()) void k_eval_fp8(EvalArgs a) {
+  eval_lp<KP, true>(a);
 }
 
 template <int KP>

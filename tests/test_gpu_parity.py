@@ -108,7 +108,8 @@ def test_evaluate_c1_random_points(dtype):
     ((7, 3, 3, 2), 1, 1, 1),           # one dwell, 15 points (< one block)
     ((611, 101, 150, 145), 5, 7, 70),  # ragged: M = 1007, K = 35, two plan tiles
     ((2000, 400, 700, 741), 17, 29, 130),  # K = 493 -> Kp = 512, three tiles
-])
+    ((300, 60, 100, 120), 20, 20, 150),    # K = 400 -> Kp = 416: BF16 / FP8 workgroups of
+])                                         # two tiles, the last one's second tile empty
 @pytest.mark.parametrize("dtype", ["f32", "f32acc64", "f32chunk64", "bf16", "fp8"])
 def test_evaluate_ragged_shapes(M_pts, n_cath, n_dw, P, dtype):
     announce(f"evaluate ragged {M_pts} {n_cath}x{n_dw} P={P} {dtype}")
@@ -224,21 +225,24 @@ def test_early_exit_compacts_stopped_plans(dtype):
     assert np.all(m["iterations"][keep] >= 1)
 
 
-def test_compacted_columns_equal_a_dense_batch():
+@pytest.mark.parametrize("shape,dtype", [("c1", "f32acc64"), ("k400", "bf16")])
+def test_compacted_columns_equal_a_dense_batch(shape, dtype):
     # A batch of 150 plans and the same plans interleaved with 42 zero-weight
     # plans (192 columns either way, so the same tile and split counts in
     # every round): the zero-weight plans stop at their first evaluation and
     # every later round packs the running plans into other columns.  A plan's
     # arithmetic does not depend on its column, so the results are identical.
-    announce("compacted columns vs dense batch")
-    c = cases.case_c1()
+    # At 400 dwells the BF16 evaluation covers two tiles per workgroup, so the
+    # three-tile rounds leave the last workgroup's second tile empty.
+    announce(f"compacted columns vs dense batch {shape} {dtype}")
+    c = cases.case_c1() if shape == "c1" else cases.make_case(20, 20, (300, 60, 100, 120), seed=416)
     Wd = cases.hidden_weights(150, seed=22)
     zero = np.zeros(192, bool)
     zero[0:168:4] = True
     Wi = np.zeros((192, Wd.shape[1]))
     Wi[~zero] = Wd
-    a = planner(c, Wi, dtype="f32acc64")
-    b = planner(c, Wd, dtype="f32acc64")
+    a = planner(c, Wi, dtype=dtype)
+    b = planner(c, Wd, dtype=dtype)
     ia = a.optimize(max_iter=40)
     ib = b.optimize(max_iter=40)
     np.testing.assert_array_equal(a.weights_x()[~zero], b.weights_x())
