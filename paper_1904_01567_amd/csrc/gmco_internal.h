@@ -12,12 +12,14 @@ namespace gmco {
 constexpr int kGmax = GMCO_MAX_GROUPS;
 constexpr int kBM = 16;   // dose points per inner block of the evaluation kernel
 constexpr int kPT = 64;   // plans per tile of the evaluation (one FP32 workgroup)
-// Plan tiles per BF16 / FP8 evaluation workgroup.  One (16 plans per
-// wavefront) lets two workgroups share a compute unit up to Kp = 384, which
-// hides more latency than two tiles (32 plans per wavefront, one workgroup)
-// save in loads; above that only one workgroup fits either way, and two tiles
-// are used where their registers fit without spilling (Kp = 416).
-__host__ __device__ constexpr int lp_tiles(int Kp) { return Kp == 416 ? 2 : 1; }
+// Shape of the BF16 / FP8 evaluation workgroup per padded dwell count:
+// threads, and 16-plan column groups per wavefront.  Up to Kp = 384 eight
+// wavefronts of 16 plans (two per SIMD) share one double-buffered LDS tile;
+// at Kp = 416 four wavefronts of 32 plans; above, four of 16 (the registers
+// of 32 plans no longer fit).  lp_tiles: the plan tiles a workgroup covers.
+__host__ __device__ constexpr int lp_threads(int Kp) { return Kp <= 384 ? 512 : 256; }
+__host__ __device__ constexpr int lp_halves(int Kp) { return Kp == 416 ? 2 : 1; }
+__host__ __device__ constexpr int lp_tiles(int Kp) { return lp_threads(Kp) / 64 * 16 * lp_halves(Kp) / kPT; }
 constexpr int kKAlign = 32;
 constexpr int kMAlign = 32;  // points: a multiple of every kernel's block
 constexpr int kSplitMax = 256;  // largest split-M count the heuristic picks
