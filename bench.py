@@ -8,14 +8,16 @@ point-source dose law) with a batch of 1,000 hidden-weight vectors
 path over that batch: upload the weights, run batched L-BFGS (m = 10) for the
 calibrated iteration count, export t = x^2 and compute the FP64 objective and
 DVH metrics of every plan.  Inputs are resident on the GPU before timing.  By
-default the first 500 accepted steps use FP32 matrix ops and the rest the
-FP64-accumulated dose (DEFAULT_LADDER); --dtype runs one arithmetic throughout.
+default the first 100 accepted steps use BF16 matrix ops, the steps up to 500
+FP32 matrix ops and the rest the FP64-accumulated dose (DEFAULT_LADDER); each
+stage resumes the plans the previous one stopped.  --dtype runs one
+arithmetic throughout.
 
 Prints one JSON line: Pareto plans per second (1000 / seconds per step), the
 roofline position of the fused evaluation kernel, and the FP64 oracle timed
 on the host cores on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--dtype f32acc64 | --ladder f32:500,f32acc64:2000]
+    python bench.py [--steps K] [--warmup W] [--dtype f32acc64 | --ladder bf16:100,f32:500,f32acc64:2000]
 """
 from __future__ import annotations
 
@@ -41,7 +43,7 @@ TIME_EVERY = 16  # rounds between timed rounds in the timed steps
 # the FP64-accumulated dose to 2,000 steps (the plan state carries over; plans
 # whose FP32 line search stalled resume).  64/64 sampled plans meet the
 # tolerance, as with the FP64-accumulated dose throughout.
-DEFAULT_LADDER = "f32:500,f32acc64:2000"
+DEFAULT_LADDER = "bf16:100,f32:500,f32acc64:2000"
 EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k_eval_f32",
                "bf16": "k_eval_bf16", "fp8": "k_eval_fp8"}
 
@@ -50,8 +52,8 @@ EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k
 # (KiB per dispatch, median of the full-batch dispatches) scaled by the same
 # counters on a 256 MiB copy (read x 2.000, write x 1.000); valid only for the
 # kernel source they were taken on (first 16 hex digits of its SHA-256).
-EVAL_TRAFFIC = {"k_eval_sha256": "54363ece17641265", "dtype": "f32acc64", "plans": 1000,
-                "fetch_kib": 21269.9, "fetch_scale": 262144.0 / 131092.4,
+EVAL_TRAFFIC = {"k_eval_sha256": "710d70b1aa636525", "dtype": "f32acc64", "plans": 1000,
+                "fetch_kib": 21267.4, "fetch_scale": 262144.0 / 131092.6,
                 "write_kib": 24708.0, "write_scale": 262144.0 / 262144.0}
 ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
 # MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
@@ -322,7 +324,8 @@ def precision_report(args) -> int:
     configs = [("f32acc64", [("f32acc64", iters)]), ("f32", [("f32", iters)]),
                ("bf16", [("bf16", iters)]), ("fp8", [("fp8", iters)]),
                ("bf16", [("bf16", 150), ("f32acc64", iters)]),
-               ("fp8", [("fp8", 150), ("f32acc64", iters)])]
+               ("fp8", [("fp8", 150), ("f32acc64", iters)]),
+               ("bf16", [("bf16", 100), ("f32", 500), ("f32acc64", iters)])]
     rows = []
     for ctx_dtype, stages in configs:
         pl = Planner(dtype=ctx_dtype, max_plans=args.plans)
