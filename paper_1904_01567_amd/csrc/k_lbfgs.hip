@@ -17,10 +17,34 @@
 namespace gmco {
 namespace {
 
+// One lane's FP64 value moved across lanes by a DPP pattern (both halves).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wavefront (all 64 lanes active), the same value in every lane:
+// within each row of 16 lanes by DPP exchanges (pairs, quads, half-row
+// mirror, row mirror; each step adds two equal-rounded operands, so every
+// lane of a row ends with the same bits), then the four row sums in row
+// order.  No LDS round-trips, so the chain of dependent dot products of the
+// two-loop recursion stays short.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
 
 template <int E>
@@ -29,6 +53,52 @@ __device__ inline double dot(const float (&a)[E], const float (&b)[E]) {
 #pragma unroll
   for (int j = 0; j < E; ++j) s = fmaf(a[j], b[j], s);
   return wave_sum((double)s);
+}
+
+// Two-loop recursion (newest to oldest, scale gamma = s'y / y'y of the
+// newest pair, oldest to newest) over hc pairs in age order; d = -H g.  With
+// NEW, pair 0 is (sn, yn, rn) and pair i the stored pair i - 1; otherwise
+// pair i is the stored pair i.  Every index is a compile-time constant, so
+// the pairs are used where they were loaded.
+template <int E, int MH, bool NEW>
+__device__ inline void two_loop(const float (&g)[E], const float (&sn)[E], const float (&yn)[E],
+                                double rn, const float (&os)[MH][E], const float (&oy)[MH][E],
+                                const double (&orr)[MH], int hc, float (&d)[E]) {
+#define GMCO_S(i) (NEW ? ((i) == 0 ? sn : os[(i) > 0 ? (i) - 1 : 0]) : os[(i)])
+#define GMCO_Y(i) (NEW ? ((i) == 0 ? yn : oy[(i) > 0 ? (i) - 1 : 0]) : oy[(i)])
+#define GMCO_R(i) (NEW ? ((i) == 0 ? rn : orr[(i) > 0 ? (i) - 1 : 0]) : orr[(i)])
+  float qv[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) qv[j] = g[j];
+  double al[MH];
+#pragma unroll
+  for (int i = 0; i < MH; ++i) {
+    al[i] = 0.0;
+    if (i < hc) {
+      al[i] = GMCO_R(i) * dot(GMCO_S(i), qv);
+      const float af = (float)al[i];
+#pragma unroll
+      for (int j = 0; j < E; ++j) qv[j] = fmaf(-af, GMCO_Y(i)[j], qv[j]);
+    }
+  }
+  const double gamma = dot(GMCO_S(0), GMCO_Y(0)) / dot(GMCO_Y(0), GMCO_Y(0));
+  const float gf = (float)gamma;
+#pragma unroll
+  for (int j = 0; j < E; ++j) qv[j] *= gf;
+#pragma unroll
+  for (int i = MH - 1; i >= 0; --i) {
+    if (i < hc) {
+      const double bi = GMCO_R(i) * dot(GMCO_Y(i), qv);
+      const float cf = (float)(al[i] - bi);
+#pragma unroll
+      for (int j = 0; j < E; ++j) qv[j] = fmaf(cf, GMCO_S(i)[j], qv[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) d[j] = -qv[j];
+#undef GMCO_S
+#undef GMCO_Y
+#undef GMCO_R
 }
 
 // MH = register capacity for history pairs (MH >= m).  The pairs are held in
@@ -61,6 +131,34 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
     x[j] = valid[j] ? a.x[row + e] : 0.f;
     g[j] = valid[j] ? a.g[row + e] : 0.f;
     d[j] = valid[j] ? a.dir[row + e] : 0.f;
+  }
+  // The stored history pairs in age order (0 = newest before this round),
+  // loaded with the other vectors so that their latency overlaps; a pair
+  // pushed this round is prepended from registers below.  (A push overwrites
+  // the oldest slot only after these loads.)
+  const int hc0 = st.hcount;
+  float ohs[MH][E], ohy[MH][E];
+  double ohr[MH];
+#pragma unroll
+  for (int i = 0; i < MH; ++i) {
+    ohr[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      ohs[i][j] = 0.f;
+      ohy[i][j] = 0.f;
+    }
+    if (i < hc0) {
+      const int slot = (st.hhead - 1 - i + 2 * m) % m;
+      const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
+      const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
+      ohr[i] = a.rho[(size_t)p * m + slot];
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        if (valid[j]) {
+          ohs[i][j] = Sd[lane + 64 * j];
+          ohy[i][j] = Yd[lane + 64 * j];
+        }
+    }
   }
   // gradient partials of this round's compact column, summed by k_reduce_g
   const RoundTable rt = *a.rt;
@@ -187,69 +285,12 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
         for (int j = 0; j < E; ++j) d[j] = -g[j];
         alpha0 = 1.0 / sqrt(gg);
       } else {
-        // history in age order; the pair pushed this round comes from registers
-        float hs[MH][E], hy[MH][E];
-        double hr[MH];
-#pragma unroll
-        for (int i = 0; i < MH; ++i) {
-          hr[i] = 0.0;
-#pragma unroll
-          for (int j = 0; j < E; ++j) {
-            hs[i][j] = 0.f;
-            hy[i][j] = 0.f;
-          }
-          if (i < hc) {
-            if (i == 0 && pushed) {
-              hr[0] = rho_new;
-#pragma unroll
-              for (int j = 0; j < E; ++j) {
-                hs[0][j] = sv[j];
-                hy[0][j] = yv[j];
-              }
-            } else {
-              const int slot = (st.hhead - 1 - i + 2 * m) % m;
-              const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
-              const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
-              hr[i] = a.rho[(size_t)p * m + slot];
-#pragma unroll
-              for (int j = 0; j < E; ++j)
-                if (valid[j]) {
-                  hs[i][j] = Sd[lane + 64 * j];
-                  hy[i][j] = Yd[lane + 64 * j];
-                }
-            }
-          }
-        }
-        // two-loop recursion: newest to oldest, scale, oldest to newest
-        float qv[E];
-#pragma unroll
-        for (int j = 0; j < E; ++j) qv[j] = g[j];
-        double al[MH];
-#pragma unroll
-        for (int i = 0; i < MH; ++i) {
-          al[i] = 0.0;
-          if (i < hc) {
-            al[i] = hr[i] * dot(hs[i], qv);
-            const float af = (float)al[i];
-#pragma unroll
-            for (int j = 0; j < E; ++j) qv[j] = fmaf(-af, hy[i][j], qv[j]);
-          }
-        }
-        const double gamma = dot(hs[0], hy[0]) / dot(hy[0], hy[0]);
-        const float gf = (float)gamma;
-#pragma unroll
-        for (int j = 0; j < E; ++j) qv[j] *= gf;
-#pragma unroll
-        for (int i = MH - 1; i >= 0; --i) {
-          if (i < hc) {
-            const double bi = hr[i] * dot(hy[i], qv);
-            const float cf = (float)(al[i] - bi);
-#pragma unroll
-            for (int j = 0; j < E; ++j) qv[j] = fmaf(cf, hs[i][j], qv[j]);
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < E; ++j) d[j] = -qv[j];
+        // history in age order: the pair pushed this round (from registers),
+        // then the stored pairs
+        if (pushed)
+          two_loop<E, MH, true>(g, sv, yv, rho_new, ohs, ohy, ohr, hc, d);
+        else
+          two_loop<E, MH, false>(g, sv, yv, rho_new, ohs, ohy, ohr, hc, d);
       }
       double gtp = dot(g, d);
       if (!(gtp < 0.0)) {  // not a descent direction: restart from -g
