@@ -521,11 +521,17 @@ def main(argv=None) -> int:
     t_load = time.perf_counter() - t_load
 
     if args.calibrate:
-        pl.set_weights(W)
+        # the run's stages from the start, the last one capped at n accepted
+        # steps (earlier caps clipped to n), for each n
         for n in [int(v) for v in args.calibrate.split(",")]:
-            info = pl.optimize(max_iter=n)
+            pl.set_weights(W)
+            ms = 0.0
+            for k, (dt, cap) in enumerate(stages):
+                c = n if k == len(stages) - 1 else min(cap, n)
+                ms += pl.optimize(max_iter=c, dtype=dt, resume_stopped=k > 0)["device_ms"]
             rep = tolerance_report(pl.metrics(), golden)
-            print(json.dumps({"iters": n, "info": info, "tol": rep}), flush=True)
+            print(json.dumps({"iters": n, "stages": [f"{d}:{min(c, n)}" for d, c in stages[:-1]] +
+                              [f"{stages[-1][0]}:{n}"], "device_ms": ms, "tol": rep}), flush=True)
         return 0
 
     def step(time_kernels=0):
