@@ -1,15 +1,16 @@
 // Fused batched evaluation of the gMCO objective and its gradient.
 //
-// For a tile of 64 plans and a range of dose points, one workgroup computes
+// For one or two tiles of 64 plans and a range of dose points, one workgroup
+// computes
 //   d   = D t                      eq. (dose), t = x^2 (Sec. 2.1.2)
 //   f   = eq. 1 per point, F += (w_j / N_j) f             eq. (obj)
 //   phi = (w_j / N_j) kappa(d)     kappa = the bracket of eq. 2
 //   G  += D^T phi                  back-projection over the points
 // and writes G and F as split-M partials; the gradient in x is 4 x * sum G
-// (eq. 2).  The dose tile never leaves the chip: each 16-point block of D is
-// staged once in LDS and feeds both products, the dwell times and the
-// gradient accumulators of the wave's 16 plans stay in registers for the
-// whole point range.
+// (eq. 2).  The dose tile never leaves the chip: each block of D (16 points
+// for FP32 operands, 32 for BF16 / FP8) is staged once in LDS and feeds both
+// products, and the dwell times and gradient accumulators of each wave's
+// plans stay in registers for the whole point range.
 //
 // Operand layout of the 16x16x4 matrix ops for lane l (q = l / 16, n = l % 16):
 // A[n][q], B[q][n].  Accumulator register r holds C[4 q + r][n] for the FP32
