@@ -10,8 +10,8 @@
 //     direction with the two-loop recursion (Liu & Nocedal, cited in
 //     Sec. 2.2.2), gamma = s'y / y'y of the newest pair, restarting from
 //     steepest descent when the direction is not a descent direction.
-// Each lane owns dwells e = lane + 64 j, so every vector operation is local
-// to the lane and every dot product is one wavefront reduction.
+// Each lane owns groups of four consecutive dwells, so every vector operation
+// is local to the lane and every dot product is one wavefront reduction.
 #include "gmco_internal.h"
 
 namespace gmco {
@@ -101,6 +101,34 @@ __device__ inline void two_loop(const float (&g)[E], const float (&sn)[E], const
 #undef GMCO_R
 }
 
+// Lane layout of a plan vector: element j of lane l is dwell
+// 4 l + 256 (j / 4) + j % 4, so each group of four elements is one 16-byte
+// access and a wavefront moves 1 KiB per instruction.  Groups at or past Kp
+// read as zero (and add nothing to a dot product) and are not written.
+template <int E>
+__device__ inline void load_vec(const float* __restrict__ src, int lane, int Kp, float (&v)[E]) {
+#pragma unroll
+  for (int c = 0; c < E / 4; ++c) {
+    const int e = 4 * lane + 256 * c;
+    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e < Kp) t = *reinterpret_cast<const float4*>(src + e);
+    v[4 * c + 0] = t.x;
+    v[4 * c + 1] = t.y;
+    v[4 * c + 2] = t.z;
+    v[4 * c + 3] = t.w;
+  }
+}
+
+template <int E>
+__device__ inline void store_vec(float* __restrict__ dst, int lane, int Kp, const float (&v)[E]) {
+#pragma unroll
+  for (int c = 0; c < E / 4; ++c) {
+    const int e = 4 * lane + 256 * c;
+    if (e < Kp)
+      *reinterpret_cast<float4*>(dst + e) = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+  }
+}
+
 // MH = register capacity for history pairs (MH >= m).  The pairs are held in
 // registers in age order (0 = newest) so every loop index is a compile-time
 // constant; all their loads are issued together before the recursion.
@@ -110,28 +138,26 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.active_count[(a.round + 1) & 1] = 0;
   if (p >= a.Pp) return;
-  PlanState st = a.ps[p];
-  if (!state_active(st.status)) return;
-
   const int Kp = a.Kp;
   const int m = a.m;
   const size_t row = (size_t)p * Kp;
-  bool valid[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) valid[j] = (lane + 64 * j) < Kp;
 
-  // ---- objective and gradient at the evaluated point ----
+  // Everything that does not depend on the plan's state is loaded together
+  // with it (the round's shape, the plan's compact column and its vectors),
+  // so that the kernel waits on two levels of loads, not three.  For a
+  // stopped plan the values are not used.
+  PlanState st = a.ps[p];
+  const RoundTable rt = *a.rt;
+  const size_t col = (size_t)a.slot[p];
   float xt[E], gt[E], x[E], g[E], d[E];
   float G[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    G[j] = 0.f;
-    const int e = lane + 64 * j;
-    xt[j] = valid[j] ? a.xt[row + e] : 0.f;
-    x[j] = valid[j] ? a.x[row + e] : 0.f;
-    g[j] = valid[j] ? a.g[row + e] : 0.f;
-    d[j] = valid[j] ? a.dir[row + e] : 0.f;
-  }
+  load_vec(a.xt + row, lane, Kp, xt);
+  load_vec(a.x + row, lane, Kp, x);
+  load_vec(a.g + row, lane, Kp, g);
+  load_vec(a.dir + row, lane, Kp, d);
+  if (!state_active(st.status)) return;
+
+  // ---- objective and gradient at the evaluated point ----
   // The stored history pairs in age order (0 = newest before this round),
   // loaded with the other vectors so that their latency overlaps; a pair
   // pushed this round is prepended from registers below.  (A push overwrites
@@ -152,24 +178,13 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
       const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
       ohr[i] = a.rho[(size_t)p * m + slot];
-#pragma unroll
-      for (int j = 0; j < E; ++j)
-        if (valid[j]) {
-          ohs[i][j] = Sd[lane + 64 * j];
-          ohy[i][j] = Yd[lane + 64 * j];
-        }
+      load_vec(Sd, lane, Kp, ohs[i]);
+      load_vec(Yd, lane, Kp, ohy[i]);
     }
   }
   // gradient partials of this round's compact column, summed by k_reduce_g
-  const RoundTable rt = *a.rt;
   const size_t stride = (size_t)rt.ntiles * kPT;
-  const size_t col = (size_t)a.slot[p];
-  {
-    const float* src = a.Gsum + col * Kp;
-#pragma unroll
-    for (int j = 0; j < E; ++j)
-      if (valid[j]) G[j] = src[lane + 64 * j];
-  }
+  load_vec(a.Gsum + col * Kp, lane, Kp, G);
   // split partials of F: one load per lane, then a fixed-order wave sum
   double fpart = 0.0;
   for (int s = lane; s < rt.S; s += 64) fpart += a.Fpart[s * stride + col];
@@ -190,11 +205,9 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
     for (int j = 0; j < E; ++j) {
       x[j] = xt[j];
       g[j] = gt[j];
-      if (valid[j]) {
-        a.x[row + lane + 64 * j] = x[j];
-        a.g[row + lane + 64 * j] = g[j];
-      }
     }
+    store_vec(a.x + row, lane, Kp, x);
+    store_vec(a.g + row, lane, Kp, g);
     st.F = Ft;
     if (!isfinite(Ft) || !isfinite(gg)) {
       st.status = ST_NONFINITE;
@@ -224,12 +237,8 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
         const int slot = st.hhead;
         float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
         float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
-#pragma unroll
-        for (int j = 0; j < E; ++j)
-          if (valid[j]) {
-            Sd[lane + 64 * j] = sv[j];
-            Yd[lane + 64 * j] = yv[j];
-          }
+        store_vec(Sd, lane, Kp, sv);
+        store_vec(Yd, lane, Kp, yv);
         rho_new = 1.0 / sy;
         if (lane == 0) a.rho[(size_t)p * m + slot] = rho_new;
         st.hhead = (slot + 1) % m;
@@ -243,11 +252,9 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       for (int j = 0; j < E; ++j) {
         x[j] = xt[j];
         g[j] = gt[j];
-        if (valid[j]) {
-          a.x[row + lane + 64 * j] = x[j];
-          a.g[row + lane + 64 * j] = g[j];
-        }
       }
+      store_vec(a.x + row, lane, Kp, x);
+      store_vec(a.g + row, lane, Kp, g);
       if (st.F == 0.0 || (st.Fprev - st.F) <= a.eps * st.Fprev) {
         st.status = ST_CONVERGED;
         stop = true;
@@ -265,9 +272,10 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       } else {
         st.alpha *= a.beta;
         const float al = (float)st.alpha;
+        float tr[E];
 #pragma unroll
-        for (int j = 0; j < E; ++j)
-          if (valid[j]) a.xt[row + lane + 64 * j] = fmaf(al, d[j], x[j]);
+        for (int j = 0; j < E; ++j) tr[j] = fmaf(al, d[j], x[j]);
+        store_vec(a.xt + row, lane, Kp, tr);
       }
     }
   }
@@ -305,19 +313,16 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
       st.alpha = alpha0;
       st.ntrial = 0;
       const float af = (float)alpha0;
+      float tr[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j)
-        if (valid[j]) {
-          a.dir[row + lane + 64 * j] = d[j];
-          a.xt[row + lane + 64 * j] = fmaf(af, d[j], x[j]);
-        }
+      for (int j = 0; j < E; ++j) tr[j] = fmaf(af, d[j], x[j]);
+      store_vec(a.dir + row, lane, Kp, d);
+      store_vec(a.xt + row, lane, Kp, tr);
     }
   }
   if (stop) {
     // the next evaluation of this plan (if any) is at its final point
-#pragma unroll
-    for (int j = 0; j < E; ++j)
-      if (valid[j]) a.xt[row + lane + 64 * j] = x[j];
+    store_vec(a.xt + row, lane, Kp, x);
   }
   if (lane == 0) {
     a.ps[p] = st;
@@ -416,18 +421,10 @@ __global__ void k_resume(PlanState* ps, const float* __restrict__ x, float* __re
 }  // namespace
 
 hipError_t launch_update(const UpdateArgs& a, hipStream_t st) {
-  const int E = (a.Kp + 63) / 64;
-  switch (E) {
-    case 1: return launch_update_e<1>(a, st);
-    case 2: return launch_update_e<2>(a, st);
-    case 3: return launch_update_e<3>(a, st);
-    case 4: return launch_update_e<4>(a, st);
-    case 5: return launch_update_e<5>(a, st);
-    case 6: return launch_update_e<6>(a, st);
-    case 7: return launch_update_e<7>(a, st);
-    case 8: return launch_update_e<8>(a, st);
-    default: return hipErrorInvalidValue;
-  }
+  // four consecutive dwells per lane and group; one or two groups
+  if (a.Kp <= 256) return launch_update_e<4>(a, st);
+  if (a.Kp <= 512) return launch_update_e<8>(a, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
