@@ -470,7 +470,7 @@ def main(argv=None) -> int:
     args.dtype = args.dtype or "f32acc64"
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
 
