@@ -74,10 +74,13 @@ def test_user_dose_rate_matrix_is_used_as_given():
 # derivative to 8 significant bits (relative 2^-9 = 2e-3 each), which moves a
 # dose near 15 Gy by ~1e-3 relative and the penalty of points near a band edge
 # by up to a few percent.
-# FP8 e4m3 keeps 3 significant bits (relative 2^-4 per element) on D and the
-# scaled dwell times; the back-projection stays BF16.
+# FP8 e4m3 keeps 4 significant bits (relative 2^-4 per rounded element) on D
+# and the scaled dwell times, so a dose is within 2 * 2^-4 = 12.5 % and the
+# penalty of eq. 1, quadratic in the deviation from the band, within about
+# twice that where the deviation is comparable to the dose: 25 % on F and on
+# the gradient (the back-projection stays BF16).
 TOL = {"f32": (2e-5, 2e-4), "f32acc64": (2e-5, 2e-4), "f32chunk64": (2e-5, 2e-4),
-       "bf16": (5e-2, 5e-2), "fp8": (0.5, 0.5)}
+       "bf16": (5e-2, 5e-2), "fp8": (0.25, 0.25)}
 
 
 def _check_eval(c, D, W, x, tag, dtype="f32"):
