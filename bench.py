@@ -22,6 +22,7 @@ on the host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import platform
 import json
 import math
 import os
@@ -465,6 +466,10 @@ def main(argv=None) -> int:
                          "sampled plans against the FP64 oracle optima")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB buffer once (reference for HBM byte counters)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the oracle's host timing (--cpu-plans x --cpu-iters), no GPU")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="BLAS threads of the host timing (0: all host cores)")
     args = ap.parse_args(argv)
     one_stage = args.dtype is not None
     args.dtype = args.dtype or "f32acc64"
@@ -473,6 +478,15 @@ def main(argv=None) -> int:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         return 2
+    if args.cpu_only:
+        import numpy  # noqa: F401  (BLAS loaded, so that the limit reaches it)
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=args.cpu_threads or None):
+            r = cpu_baseline(args.cpu_plans, args.cpu_iters, args.iters or 2000)
+        print(json.dumps({"cpu_baseline": r, "s_per_plan": 1.0 / r["value"],
+                          "host_cpu": platform.processor() or platform.machine(),
+                          "host_cores": os.cpu_count()}), flush=True)
+        return 0
 
     import numpy as np
     import torch
