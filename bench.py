@@ -590,6 +590,8 @@ def main(argv=None) -> int:
     achieved = work * flops_full / (eval_ms / 1e3) / 1e12
     peak = eval_peak_tflops(stages[-1][0])
     tol = tolerance_report(m, golden)
+    # selection over the plans of the last timed step (after the timed region)
+    _, _, _, nd_frac = pl.select_plan()
     upd_ms = sum(i["update_ms"] for i in infos)
 
     out = {
@@ -614,6 +616,7 @@ def main(argv=None) -> int:
             "lbfgs_history": 10, "stages": [f"{d}:{n}" for d, n in stages],
         },
         "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
+        "nondominated_fraction": nd_frac,
         "breakdown_per_step": {
             "eval_us_per_launch": 1e3 * sum(i["eval_ms"] for i in infos) / max(1, sum(i["timed_launches"] for i in infos)),
             "reduce_update_us_per_round": 1e3 * upd_ms / max(1, sum(i["timed_launches"] for i in infos)),
