@@ -183,6 +183,30 @@ def test_first_iterations_follow_the_oracle(k):
     assert info["n_maxiter"] == W.shape[0]
 
 
+def test_first_iterations_at_the_largest_dwell_count():
+    # 493 dwells (Kp = 512, the largest padded size): every lane of the update
+    # kernel holds two full groups of four dwells, and the evaluation runs its
+    # widest tiles; the first steps follow the oracle as on the small case.
+    announce("trajectory at Kp = 512")
+    c = cases.make_case(17, 29, (2000, 400, 700, 741), seed=3841)
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    W = cases.hidden_weights(70, seed=70)
+    k = 3
+    x0 = O.default_start(D, c.group, 15.0, W.shape[0])
+    pl = planner(c, W)
+    info = pl.optimize(max_iter=k)
+    xg = pl.weights_x()
+    r = O.optimize(D, c.group, PARAMS, W, x0, O.LbfgsOptions(max_iter=k))
+    m = pl.metrics()
+    np.testing.assert_array_equal(m["iterations"], r["iters"])
+    np.testing.assert_array_equal(m["evaluations"], r["evals"])
+    err = np.abs(xg - r["x"]).max(axis=1) / np.abs(r["x"]).max(axis=1)
+    announce(f"Kp=512: x rel err {err.max():.2e}; F rel {np.max(np.abs(m['F_run'] / r['F'] - 1)):.2e}")
+    assert err.max() <= 1e-3 * k
+    np.testing.assert_allclose(m["F_run"], r["F"], rtol=2e-5 * k)
+    assert info["n_maxiter"] == W.shape[0]
+
+
 def test_many_tiles_sampled_plans_follow_the_oracle():
     # 4100 plans = 65 tiles (the last ragged): each compacted round spreads
     # the tiles over many workgroups; plans are independent, so the oracle
