@@ -252,6 +252,26 @@ def test_early_exit_compacts_stopped_plans(dtype):
     assert np.all(m["iterations"][keep] >= 1)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_early_exit_compacts_at_the_largest_dwell_count(dtype):
+    # 493 dwells (Kp = 512): the BF16 / FP8 evaluation runs 256-thread
+    # workgroups of one plan tile; with 150 plans (three tiles, the last
+    # ragged) stopping at different steps, every round evaluates exactly the
+    # plans still running.
+    announce(f"early exit and compaction at Kp = 512 {dtype}")
+    c = cases.make_case(17, 29, (2000, 400, 700, 741), seed=3841)
+    W = cases.hidden_weights(150, seed=24)
+    W[3] = 0.0
+    pl = planner(c, W, dtype=dtype)
+    info = pl.optimize(max_iter=200, eps=1e-4)
+    m = pl.metrics()
+    announce(f"{dtype}: work {info['eval_work']:.1f} in {info['rounds']} rounds")
+    assert info["eval_work"] * W.shape[0] == pytest.approx(float(m["evaluations"].sum()), abs=1e-6)
+    assert info["eval_work"] < 0.8 * info["rounds"]
+    assert m["status"][3] == O.CONVERGED and m["iterations"][3] == 0
+    assert np.all(np.isin(m["status"], [O.CONVERGED, O.MAXITER, O.LS_FAIL]))
+
+
 @pytest.mark.parametrize("shape,dtype", [("c1", "f32acc64"), ("k400", "bf16")])
 def test_compacted_columns_equal_a_dense_batch(shape, dtype):
     # A batch of 150 plans and the same plans interleaved with 42 zero-weight
