@@ -62,6 +62,26 @@ def test_graph_replays_with_early_exit_match_eager():
         assert x["eval_work"] == y["eval_work"] < x["rounds"]
 
 
+def test_bf16_batched_and_replayed_rounds_match_single_case_runs():
+    # The same three uneven cases in BF16 (workgroups of two plan tiles, a
+    # different dwell count per case) with the stop rule on: lockstep rounds,
+    # plain or replayed from a graph, equal each case run alone bit for bit.
+    # (BF16 line searches stall early, so only the identity is checked.)
+    from paper_1904_01567_amd import optimize_many
+    announce("batched vs single, BF16")
+    single = _planners("bf16")
+    for pl in single:
+        pl.optimize(max_iter=80, eps=1e-4)
+    ref = [(pl.weights_x(), pl.metrics()["iterations"]) for pl in single]
+    for R in (0, 6):
+        batch = _planners("bf16")
+        optimize_many(batch, max_iter=80, eps=1e-4, rounds_per_graph=R)
+        for k, pl in enumerate(batch):
+            np.testing.assert_array_equal(pl.weights_x(), ref[k][0])
+            np.testing.assert_array_equal(pl.metrics()["iterations"], ref[k][1])
+        announce(f"BF16, rounds_per_graph={R}: identical to single-case runs")
+
+
 def test_graph_replays_match_eager_at_every_stage():
     from paper_1904_01567_amd import optimize_many
     announce("graph replays vs eager")
