@@ -1,12 +1,20 @@
-"""Write the FP64 oracle's converged optima for sampled plans of the
-paper-scale case (360 dwells, 20,000 points, 1,000 weight vectors).
+"""Write the FP64 oracle's converged optima for the paper-scale case (360
+dwells, 20,000 points, 1,000 weight vectors).
 
-Calls only the oracle and the seeded case generator.  Output:
-tests/golden/c2_reference_optima.json with, per sampled plan, the converged
-objective F* (eq. (obj)), its DVH metrics, the oracle's iteration count and
-its objective after selected numbers of accepted steps.
+Calls only the oracle and the seeded case generator.  Two outputs:
 
-    python tests/golden/make_reference_optima.py [--max-iter 8000]
+* tests/golden/c2_reference_optima.json (default): 64 sampled plans with the
+  converged objective F* (eq. (obj)), their DVH metrics, the oracle's
+  iteration count and the objective after selected numbers of accepted steps;
+* tests/golden/c2_reference_optima_all.json (--all): every one of the 1,000
+  plans, compactly (F*, per-organ V100 / D10 / V75 and individual objectives,
+  iterations, status), computed by --workers processes that each run the
+  oracle on a contiguous share of the plans with one BLAS thread.  Plans are
+  independent (Sec. 2.2.1), so the share a plan is run in does not change its
+  optimum.
+
+    python tests/golden/make_reference_optima.py [--max-iter 20000]
+    python tests/golden/make_reference_optima.py --all --workers 8
 """
 import argparse
 import json
@@ -30,26 +38,63 @@ SAMPLE = SAMPLE + sorted(np.random.default_rng(77).choice(_rest, 48, replace=Fal
 # accepted-step counts at which each plan's objective is recorded
 CHECKPOINTS = [25, 50, 100, 150, 200, 300, 400, 500, 750, 1000, 1250, 1500, 2000, 2500, 3000,
                4000, 5000, 6000, 8000, 10000, 12000, 16000, 20000]
+EPS = 1e-15
+WORKLOAD = ("synthetic prostate case: 18 catheters x 20 dwells (360), 20,000 points "
+            "(10000/2000/4000/4000), seed 2; weights log-uniform [0.1, 10], seed 12")
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--max-iter", type=int, default=20000)
-    ap.add_argument("--out", default=os.path.join(HERE, "c2_reference_optima.json"))
-    args = ap.parse_args(argv)
+def _run(plans, max_iter):
     c = cases.case_c2()
-    W = cases.weights_c2()[SAMPLE]
+    W = cases.weights_c2()[plans]
     D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
-    x0 = O.default_start(D, c.group, c.prescription_gy, len(SAMPLE))
-    t0 = time.time()
+    x0 = O.default_start(D, c.group, c.prescription_gy, len(plans))
     r = O.optimize(D, c.group, O.CLASS_SOLUTION_VOLUME, W, x0,
-                   O.LbfgsOptions(max_iter=args.max_iter, eps=1e-15))
+                   O.LbfgsOptions(max_iter=max_iter, eps=EPS))
     m = O.plan_metrics(D, r["t"], c.group, O.CLASS_SOLUTION_VOLUME, W, c.volume_cc,
                        c.prescription_gy)
+    return r, m
+
+
+def _share(job):
+    """One worker: the oracle on plans lo..hi-1 with one BLAS thread."""
+    lo, hi, max_iter = job
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        r, m = _run(list(range(lo, hi)), max_iter)
+    print(f"plans {lo}-{hi - 1} done in {time.time() - t0:.0f} s", flush=True)
+    return dict(F=r["F"].tolist(), iters=r["iters"].tolist(), status=r["status"].tolist(),
+                V100_pct=[q["V100_pct"].tolist() for q in m],
+                D10_pct=[q["D10_pct"].tolist() for q in m],
+                V75_cc=[q["V75_cc"].tolist() for q in m],
+                f_organ=[q["f_organ"].tolist() for q in m])
+
+
+def write_all(args):
+    import multiprocessing as mp
+    n = 1000
+    bounds = np.linspace(0, n, args.workers + 1).astype(int)
+    jobs = [(int(a), int(b), args.max_iter) for a, b in zip(bounds[:-1], bounds[1:])]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(args.workers) as pool:
+        parts = pool.map(_share, jobs)
+    out = dict(workload=WORKLOAD,
+               options=dict(m=10, max_iter=args.max_iter, eps=EPS, c1=1e-4, beta=0.5, max_ls=30),
+               seconds=time.time() - t0, workers=args.workers, plans=n)
+    for key in ("F", "iters", "status", "V100_pct", "D10_pct", "V75_cc", "f_organ"):
+        out[key] = [v for p in parts for v in p[key]]
+    path = args.out or os.path.join(HERE, "c2_reference_optima_all.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, separators=(",", ":"))
+    print(f"wrote {path} in {out['seconds']:.0f} s")
+
+
+def write_sample(args):
+    t0 = time.time()
+    r, m = _run(SAMPLE, args.max_iter)
     out = dict(
-        workload="synthetic prostate case: 18 catheters x 20 dwells (360), 20,000 points "
-                 "(10000/2000/4000/4000), seed 2; weights log-uniform [0.1, 10], seed 12",
-        options=dict(m=10, max_iter=args.max_iter, eps=1e-15, c1=1e-4, beta=0.5, max_ls=30),
+        workload=WORKLOAD,
+        options=dict(m=10, max_iter=args.max_iter, eps=EPS, c1=1e-4, beta=0.5, max_ls=30),
         seconds=time.time() - t0,
         plans=[dict(index=int(p), F=float(r["F"][j]), iters=int(r["iters"][j]),
                     status=int(r["status"][j]),
@@ -60,9 +105,23 @@ def main(argv=None):
                           for k in CHECKPOINTS})
                for j, p in enumerate(SAMPLE)],
     )
-    with open(args.out, "w") as fh:
+    path = args.out or os.path.join(HERE, "c2_reference_optima.json")
+    with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(f"wrote {args.out} in {out['seconds']:.0f} s")
+    print(f"wrote {path} in {out['seconds']:.0f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--all", action="store_true", help="every plan of the batch, compact form")
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    if args.all:
+        write_all(args)
+    else:
+        write_sample(args)
 
 
 if __name__ == "__main__":

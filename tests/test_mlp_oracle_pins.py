@@ -47,6 +47,37 @@ def test_adam_one_step_by_hand():
     np.testing.assert_allclose(v1, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_closed_form():
+    # With a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step (m_n = (1 - b1^n) g, v_n = (1 - b2^n) g^2), so each of
+    # n steps moves the parameter by lr g / (|g| + eps): a pin of both bias
+    # corrections at every step count, not only the first.
+    g = np.array([0.5, -4.0, 1e-3, 7.0])
+    p0 = np.array([1.0, -2.0, 0.3, 0.0])
+    lr = 0.01
+    p, m, v = p0.copy(), np.zeros(4), np.zeros(4)
+    for n in range(1, 41):
+        p, m, v = M.adam_step(p, g, m, v, n, lr=lr)
+        np.testing.assert_allclose(m, (1 - 0.9 ** n) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1 - 0.999 ** n) * g * g, rtol=1e-12)
+        np.testing.assert_allclose(p, p0 - n * lr * g / (np.abs(g) + 1e-8), rtol=1e-10, atol=1e-14)
+
+
+def test_adam_two_gradients_by_hand():
+    # step 1 with g1, step 2 with g2, written out from the definitions:
+    # m2 = b1 (1 - b1) g1 + (1 - b1) g2, v2 = b2 (1 - b2) g1^2 + (1 - b2) g2^2,
+    # update = lr (m2 / (1 - b1^2)) / (sqrt(v2 / (1 - b2^2)) + eps)
+    g1, g2 = np.array([2.0, -1.0]), np.array([-1.0, 3.0])
+    p = np.array([0.0, 0.0])
+    p1, m, v = M.adam_step(p, g1, np.zeros(2), np.zeros(2), 1, lr=0.1)
+    p2, m, v = M.adam_step(p1, g2, m, v, 2, lr=0.1)
+    m2 = 0.9 * 0.1 * g1 + 0.1 * g2
+    v2 = 0.999 * 0.001 * g1 ** 2 + 0.001 * g2 ** 2
+    u1 = 0.1 * np.sign(g1) * np.abs(g1) / (np.abs(g1) + 1e-8)
+    u2 = 0.1 * (m2 / (1 - 0.81)) / (np.sqrt(v2 / (1 - 0.999 ** 2)) + 1e-8)
+    np.testing.assert_allclose(p2, -u1 - u2, rtol=1e-12)
+
+
 def test_features_brute_force_and_invariants():
     c = cases.small_case()
     f = M.case_features(c.dwell_xyz, c.pt_xyz, c.group)
@@ -60,9 +91,19 @@ def test_features_brute_force_and_invariants():
         r = min(math.dist(q, p) for p in pts)
         hist[min(int(r // 0.25), 15)] += 1
     np.testing.assert_allclose(f.reshape(4, 16)[j], hist / c.K, rtol=0, atol=1e-15)
-    # translating the whole case leaves the features unchanged
-    shift = np.array([0.0, 0.0, 0.0])
+    # translating the whole case leaves the features unchanged (distances
+    # change only by rounding, far from the 0.25 cm bin edges)
+    shift = np.array([0.37, -1.25, 2.5])
     np.testing.assert_array_equal(M.case_features(c.dwell_xyz + shift, c.pt_xyz + shift, c.group), f)
+    # so does a quarter turn about z, (x, y) -> (-y, x): it only swaps the
+    # two squared terms of each distance, which FP64 addition commutes exactly
+    rot = lambda a: np.stack([-a[:, 1], a[:, 0], a[:, 2]], axis=1)
+    np.testing.assert_array_equal(M.case_features(rot(c.dwell_xyz), rot(c.pt_xyz), c.group), f)
+    # while moving one structure away from the dwells changes its histogram
+    moved = c.pt_xyz.copy()
+    moved[c.group == j] += np.array([0.0, 0.0, 10.0])
+    g = M.case_features(c.dwell_xyz, moved, c.group).reshape(4, 16)
+    assert g[j, 15] == 1.0 and not np.array_equal(g[j], f.reshape(4, 16)[j])
 
 
 def test_init_layout():
