@@ -203,15 +203,18 @@ int gmco_load_case(gmco_ctx* ctx, const gmco_case* c);
 /* Set the hidden-weight batch, eq. (obj): W is P x n_organs (n_groups without
  * group_organ), finite and >= 0,
  * used as given (normalise rows to sum 1 beforehand for the paper's weighted
- * sum).  t0 is P x K start dwell times (> 0 recommended: x_l = 0 is a fixed
- * point of the x^2 substitution) or NULL for the uniform start t_bar.  Resets
- * every plan to its start.  Errors: EINVAL (P out of 1..max_plans, bad value),
+ * sum).  t0 is P x K start dwell times, finite and > 0 (x_l = 0 is a fixed
+ * point of the x^2 substitution of Sec. 2.1.2: the gradient of eq. 2 is
+ * proportional to x_l), or NULL for the uniform start t_bar.  Resets every
+ * plan to its start.  Errors: EINVAL (P out of 1..max_plans, bad value),
  * ESTATE (no case loaded), EHIP. */
 int gmco_set_weights(gmco_ctx* ctx, int n_plans, const double* W, const double* t0);
 
 /* One batched evaluation of eq. (obj) and of its gradient in the dwell
  * weights (eq. 2 summed over points) at x (P x K, P = current batch size), in
- * the run dtype with FP32 accumulation.  F is P, g is P x K.  Uses the same
+ * the context's dtype with that dtype's accumulation (see gmco_dtype: FP32
+ * for F32, BF16 and FP8; the dose in FP64 for F32_ACC64 and F32_CHUNK64; the
+ * back-projection always in FP32).  F is P, g is P x K.  Uses the same
  * kernels as the optimiser and leaves the optimiser state untouched.
  * Errors: ESTATE, EINVAL, EHIP. */
 int gmco_evaluate(gmco_ctx* ctx, const double* x, double* F, double* g);
@@ -272,6 +275,28 @@ int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* be
  * both kernel families; otherwise the autotuner's scope.  1 <= split <= the
  * autotuner's range. */
 int gmco_set_split(gmco_ctx* ctx, int split);
+
+/* Checkpoint of the optimiser (project extension; the paper has none).  The
+ * state is the weight batch and, per plan, the L-BFGS state machine
+ * (objective, previous objective, trial step, g'p, status, counters), x, g,
+ * the search direction, the pending trial point, the history ring (s, y,
+ * rho) and the context's split counts.  It does not include the case: the
+ * restoring context must hold a case of the same shape (dwells, history
+ * length, groups and organs; normally the same case, loaded with
+ * gmco_load_case).  A gmco_optimize after gmco_set_state continues exactly as
+ * the saved context would have (the same kernels on the same values, bitwise).
+ *   gmco_state_bytes: size of the blob of the current batch.  ESTATE without a
+ *     weight batch.
+ *   gmco_get_state: write the blob to host memory owned by the caller
+ *     (`bytes` >= gmco_state_bytes, else EINVAL).  ESTATE without a batch.
+ *   gmco_set_state: restore a blob; it replaces the weight batch (the batch
+ *     size becomes the blob's).  ESTATE without a case; EINVAL for a blob of
+ *     another library version or case shape, a truncated one, or more plans
+ *     than max_plans.  Layout: a 64-byte header, then plan-major arrays; it is
+ *     private to this library version. */
+int gmco_state_bytes(const gmco_ctx* ctx, size_t* bytes);
+int gmco_get_state(gmco_ctx* ctx, void* blob, size_t bytes);
+int gmco_set_state(gmco_ctx* ctx, const void* blob, size_t bytes);
 
 /* t = x^2 of every plan, P x K, FP64 (computed on the device). */
 int gmco_get_dwell_times(gmco_ctx* ctx, double* t);
@@ -334,6 +359,24 @@ int gmco_mlp_train(gmco_mlp* net, int n_steps, int B, const int32_t* order, floa
 /* Y (B x n_out) = network(X (B x n_in)); any B, processed in max_batch chunks. */
 int gmco_mlp_predict(gmco_mlp* net, int B, const float* X, float* Y);
 const char* gmco_mlp_last_error(const gmco_mlp* net);
+
+/* Set the weight batch with the learned start: like gmco_set_weights, then
+ * for each plan the network (inputs: the plan's n_organs hidden weights as
+ * given, then the case's n_organs x 16 features of gmco_case_features;
+ * outputs: n_dwells values x_hat, the dwell weights normalised by the
+ * uniform start's sqrt(t_bar)) gives the start x0 = max(x_hat, x_floor)
+ * sqrt(t_bar) (x = 0 is a fixed point of the x^2 substitution, Sec. 2.1.2).
+ * Plain L-BFGS from the uniform start is the fallback: a plan keeps the
+ * learned start only where eq. (obj) there (context dtype) is finite and
+ * below its value at the uniform start.  Features, network and both
+ * evaluations run on the device, on the context stream.  use_warm (P ints,
+ * 1 = learned start kept) and n_warm may be NULL.  The network must have
+ * 17 x n_organs inputs and n_dwells outputs and live on the context's device;
+ * the call uses its activation buffers, so it must not overlap other work of
+ * the network.  (Project extension.)  Errors: as gmco_set_weights, EINVAL
+ * (network shape or device, x_floor <= 0, a case without point positions). */
+int gmco_set_weights_learned(gmco_ctx* ctx, gmco_mlp* net, int n_plans, const double* W, double x_floor,
+                             int* use_warm, int* n_warm);
 
 #ifdef __cplusplus
 }

@@ -28,10 +28,12 @@ EXPORTS = (
     "gmco_bind_workspace", "gmco_load_case", "gmco_set_weights", "gmco_evaluate",
     "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
     "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_optimize_many",
-    "gmco_autotune", "gmco_set_split", "gmco_select_plan", "gmco_last_error",
+    "gmco_autotune", "gmco_set_split", "gmco_select_plan", "gmco_state_bytes",
+    "gmco_get_state", "gmco_set_state", "gmco_last_error",
     "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
     "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
     "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
+    "gmco_set_weights_learned",
 )
 
 
@@ -132,6 +134,9 @@ def load_library(path: Optional[str] = None):
     lib.gmco_set_split.argtypes = [vp, C.c_int]
     lib.gmco_select_plan.argtypes = [vp, C.POINTER(gmco_select_opts), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+    lib.gmco_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.gmco_get_state.argtypes = [vp, vp, C.c_size_t]
+    lib.gmco_set_state.argtypes = [vp, vp, C.c_size_t]
     fp = C.POINTER(C.c_float)
     lib.gmco_mlp_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int]
     lib.gmco_mlp_destroy.argtypes = [vp]
@@ -143,6 +148,8 @@ def load_library(path: Optional[str] = None):
     lib.gmco_mlp_set_data.argtypes = [vp, C.c_int, fp, fp]
     lib.gmco_mlp_train.argtypes = [vp, C.c_int, C.c_int, C.POINTER(C.c_int32), C.c_float, dp]
     lib.gmco_mlp_predict.argtypes = [vp, C.c_int, fp, fp]
+    lib.gmco_set_weights_learned.argtypes = [vp, vp, C.c_int, dp, C.c_double, C.POINTER(C.c_int),
+                                             C.POINTER(C.c_int)]
     lib.gmco_mlp_last_error.argtypes = [vp]
     lib.gmco_mlp_last_error.restype = C.c_char_p
     lib.gmco_last_error.argtypes = [vp]
@@ -290,6 +297,21 @@ class Planner:
         self._check(self.lib.gmco_set_weights(self._ctx, P, _dptr(W), _dptr(t0a)), "set_weights")
         self.P = P
 
+    def set_weights_learned(self, net: "Network", W, x_floor: float = 1e-3) -> np.ndarray:
+        """Weight batch with the learned start (gmco_set_weights_learned);
+        returns, per plan, whether the learned start was kept."""
+        W = _f64(W)
+        P = W.shape[0]
+        if W.shape != (P, self.O):
+            raise ValueError(f"W must be (P, {self.O})")
+        use = np.zeros(P, dtype=np.int32)
+        n = C.c_int()
+        self._check(self.lib.gmco_set_weights_learned(self._ctx, net._net, P, _dptr(W), float(x_floor),
+                                                      use.ctypes.data_as(C.POINTER(C.c_int)), C.byref(n)),
+                    "set_weights_learned")
+        self.P = P
+        return use.astype(bool)
+
     def evaluate(self, x):
         x = _f64(x, (self.P, self.K))
         F = np.empty(self.P)
@@ -360,6 +382,21 @@ class Planner:
         self._check(self.lib.gmco_select_plan(self._ctx, None, C.byref(best), cls.ctypes.data_as(ip),
                                               nd.ctypes.data_as(ip), C.byref(frac)), "select_plan")
         return int(best.value), cls, nd.astype(bool), float(frac.value)
+
+    def get_state(self) -> bytes:
+        """Checkpoint blob of the optimiser state (gmco_get_state)."""
+        n = C.c_size_t()
+        self._check(self.lib.gmco_state_bytes(self._ctx, C.byref(n)), "state_bytes")
+        buf = C.create_string_buffer(int(n.value))
+        self._check(self.lib.gmco_get_state(self._ctx, buf, n.value), "get_state")
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        """Restore a checkpoint blob (gmco_set_state) into this context's case."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(self.lib.gmco_set_state(self._ctx, buf, len(blob)), "set_state")
+        P = int(np.frombuffer(bytes(blob[8:12]), dtype=np.int32)[0])
+        self.P = P
 
     def case_features(self) -> np.ndarray:
         out = np.empty(self.O * 16, dtype=np.float32)

@@ -26,6 +26,7 @@ struct Layout {
   size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, flag, slot, rt,
       split_tab;
   size_t t64, d64, metrics, hist, feat, sel;
+  size_t mlpX, mlpY, Fu, usewarm, nwarm;
   size_t total;
 };
 
@@ -231,6 +232,11 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.hist = take(kGmax * 16 * 4);
   L.sel = take((size_t)d.Pp * 3 * 4 + 16);
   L.feat = take(kGmax * 16 * 4);
+  L.mlpX = take((size_t)Pmax * 17 * kGmax * 4);  // network inputs: weights + 16 features per organ
+  L.mlpY = take((size_t)Pmax * d.K * 4);
+  L.Fu = take((size_t)Pmax * 8);
+  L.usewarm = take((size_t)Pmax * 4);
+  L.nwarm = take(sizeof(int));
   (void)G;
   L.total = off;
   return L;
@@ -597,7 +603,7 @@ int gmco_set_weights(gmco_ctx* c, int P, const double* W, const double* t0) {
     if (!std::isfinite(W[i]) || W[i] < 0.0) return fail(c, GMCO_EINVAL, "weights must be finite and >= 0");
   if (t0) {
     for (size_t i = 0; i < (size_t)P * K; ++i)
-      if (!std::isfinite(t0[i]) || t0[i] < 0.0) return fail(c, GMCO_EINVAL, "t0 must be finite and >= 0");
+      if (!std::isfinite(t0[i]) || !(t0[i] > 0.0)) return fail(c, GMCO_EINVAL, "t0 must be finite and > 0");
   }
   GMCO_HIP(c, hipSetDevice(c->device));
   const Layout& L = c->lay;
@@ -631,6 +637,53 @@ int gmco_evaluate(gmco_ctx* c, const double* x, double* F, double* g) {
   GMCO_HIP(c, hipMemcpyAsync(F, c->at<void>(L.Fst), (size_t)P * 8, hipMemcpyDeviceToHost, c->stream));
   GMCO_HIP(c, hipMemcpyAsync(g, c->at<void>(L.gst), (size_t)P * K * 8, hipMemcpyDeviceToHost, c->stream));
   GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+int gmco_set_weights_learned(gmco_ctx* c, gmco_mlp* net, int P, const double* W, double x_floor, int* use_warm,
+                             int* n_warm) {
+  if (!c || !net || !W) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  if (!c->has_points) return fail(c, GMCO_EINVAL, "the learned start needs point positions (case features)");
+  if (!(x_floor > 0.0) || !std::isfinite(x_floor)) return fail(c, GMCO_EINVAL, "x_floor must be finite and > 0");
+  if (mlp_device(net) != c->device) return fail(c, GMCO_EINVAL, "network and context on different devices");
+  if (mlp_inputs(net) != c->O * 17 || mlp_outputs(net) != c->dim.K)
+    return fail(c, GMCO_EINVAL, "network needs 17 x n_organs inputs and n_dwells outputs");
+  // the uniform start first (validates P and W)
+  int rc = gmco_set_weights(c, P, W, nullptr);
+  if (rc) return rc;
+  const Layout& L = c->lay;
+  const Dims& d = c->dim;
+  // objective at the uniform start
+  EvalArgs a = eval_args(c, c->at<float>(L.x), false, c->dtype);
+  GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+  GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, a.x, a.S, P, d.Pp, d.K, d.Kp, c->at<double>(L.Fu),
+                                 c->at<double>(L.gst), c->stream));
+  // network inputs (weights, case features), its prediction, the floored start
+  const double* dw = c->at<double>(L.stage) + (size_t)d.M * d.K;
+  const double* pts = dw + (size_t)d.K * 3;
+  GMCO_HIP(c, launch_features(dw, pts, c->at<int>(L.perm), c->at<int>(L.goff), c->at<int>(L.gcnt), d.K, c->O,
+                              c->at<unsigned>(L.hist), c->at<float>(L.feat), c->stream));
+  GMCO_HIP(c, launch_learned_inputs(c->at<double>(L.W64), c->at<float>(L.feat), P, c->O, c->at<float>(L.mlpX),
+                                    c->stream));
+  GMCO_HIP(c, mlp_forward_device(net, P, c->at<float>(L.mlpX), c->at<float>(L.mlpY), c->stream));
+  GMCO_HIP(c, launch_learned_start(c->at<float>(L.mlpY), P, d.Pp, d.K, d.Kp, c->at<double>(L.t_bar), x_floor,
+                                   c->at<float>(L.xe), c->stream));
+  // objective at the learned start, and the choice per plan
+  a = eval_args(c, c->at<float>(L.xe), false, c->dtype);
+  GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+  GMCO_HIP(c, launch_finish_eval(a.Gpart, a.Fpart, a.x, a.S, P, d.Pp, d.K, d.Kp, c->at<double>(L.Fst),
+                                 c->at<double>(L.gst), c->stream));
+  int* nw = c->at<int>(L.nwarm);
+  GMCO_HIP(c, hipMemsetAsync(nw, 0, sizeof(int), c->stream));
+  GMCO_HIP(c, launch_pick_start(c->at<double>(L.Fst), c->at<double>(L.Fu), c->at<float>(L.xe), P, d.Kp,
+                                c->at<float>(L.x), c->at<float>(L.xt), nw, c->at<int>(L.usewarm), c->stream));
+  int h = 0;
+  GMCO_HIP(c, hipMemcpyAsync(&h, nw, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (use_warm)
+    GMCO_HIP(c, hipMemcpyAsync(use_warm, c->at<int>(L.usewarm), (size_t)P * 4, hipMemcpyDeviceToHost, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  if (n_warm) *n_warm = h;
   return GMCO_OK;
 }
 
@@ -891,6 +944,123 @@ int gmco_set_split(gmco_ctx* c, int split) {
   if (split < 1 || split > c->dim.S_cap || split > c->dim.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
   c->dim.S = c->dim.S_lp = split;
   c->dim.S_tuned = c->dim.S_tuned_lp = split;
+  return GMCO_OK;
+}
+
+namespace {
+// Checkpoint blob: this header, then the first P rows of each plan-major
+// array in the order of state_arrays().
+struct StateHeader {
+  uint32_t magic, version;
+  int32_t P, K, Kp, m, O, G;
+  int32_t S, S_lp, S_tuned, S_tuned_lp;
+  uint64_t bytes;
+  int32_t plan_state_bytes, pad;
+};
+static_assert(sizeof(StateHeader) == 64, "state header layout");
+constexpr uint32_t kStateMagic = 0x53434d47u;  // "GMCS"
+constexpr uint32_t kStateVersion = 1;
+
+struct StateArray {
+  size_t off;       // arena offset
+  size_t row;       // bytes per plan
+};
+
+std::vector<StateArray> state_arrays(const gmco_ctx* c) {
+  const Layout& L = c->lay;
+  const size_t Kp = (size_t)c->dim.Kp, m = (size_t)c->m;
+  return {{L.ps, sizeof(PlanState)}, {L.W64, kGmax * 8}, {L.wn, kGmax * 4},
+          {L.x, Kp * 4},  {L.g, Kp * 4},  {L.dir, Kp * 4}, {L.xt, Kp * 4},
+          {L.Sh, m * Kp * 4}, {L.Yh, m * Kp * 4}, {L.rho, m * 8}};
+}
+
+size_t state_size(const gmco_ctx* c, int P) {
+  size_t n = sizeof(StateHeader);
+  for (const StateArray& a : state_arrays(c)) n += a.row * (size_t)P;
+  return n;
+}
+}  // namespace
+
+int gmco_state_bytes(const gmco_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return GMCO_ESTATE;
+  *bytes = state_size(c, c->P);
+  return GMCO_OK;
+}
+
+int gmco_get_state(gmco_ctx* c, void* blob, size_t bytes) {
+  if (!c || !blob) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  const size_t need = state_size(c, c->P);
+  if (bytes < need) return fail(c, GMCO_EINVAL, "state buffer smaller than gmco_state_bytes");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.P = c->P;
+  h.K = c->dim.K;
+  h.Kp = c->dim.Kp;
+  h.m = c->m;
+  h.O = c->O;
+  h.G = c->G;
+  h.S = c->dim.S;
+  h.S_lp = c->dim.S_lp;
+  h.S_tuned = c->dim.S_tuned;
+  h.S_tuned_lp = c->dim.S_tuned_lp;
+  h.bytes = need;
+  h.plan_state_bytes = (int32_t)sizeof(PlanState);
+  char* out = static_cast<char*>(blob);
+  std::memcpy(out, &h, sizeof(h));
+  size_t pos = sizeof(h);
+  for (const StateArray& a : state_arrays(c)) {
+    const size_t n = a.row * (size_t)c->P;
+    GMCO_HIP(c, hipMemcpyAsync(out + pos, c->at<void>(a.off), n, hipMemcpyDeviceToHost, c->stream));
+    pos += n;
+  }
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  return GMCO_OK;
+}
+
+int gmco_set_state(gmco_ctx* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  StateHeader h{};
+  if (bytes < sizeof(h)) return fail(c, GMCO_EINVAL, "state blob too small");
+  std::memcpy(&h, blob, sizeof(h));
+  if (h.magic != kStateMagic || h.version != kStateVersion || h.plan_state_bytes != (int32_t)sizeof(PlanState))
+    return fail(c, GMCO_EINVAL, "not a state blob of this library version");
+  if (h.K != c->dim.K || h.Kp != c->dim.Kp || h.m != c->m || h.O != c->O || h.G != c->G)
+    return fail(c, GMCO_EINVAL, "state blob of another case shape or history length");
+  if (h.P < 1 || h.P > c->Pmax) return fail(c, GMCO_EINVAL, "state blob holds more plans than max_plans");
+  const size_t need = state_size(c, h.P);
+  if (h.bytes != need || bytes < need) return fail(c, GMCO_EINVAL, "state blob truncated");
+  if (h.S < 1 || h.S > c->dim.S_cap || h.S_lp < 1 || h.S_lp > c->dim.S_cap || h.S_tuned < 0 ||
+      h.S_tuned > c->dim.S_cap || h.S_tuned_lp < 0 || h.S_tuned_lp > c->dim.S_cap)
+    return fail(c, GMCO_EINVAL, "state blob split counts out of range");
+  GMCO_HIP(c, hipSetDevice(c->device));
+  const char* in = static_cast<const char*>(blob);
+  size_t pos = sizeof(h);
+  for (const StateArray& a : state_arrays(c)) {
+    const size_t n = a.row * (size_t)h.P;
+    GMCO_HIP(c, hipMemcpyAsync(c->at<void>(a.off), in + pos, n, hipMemcpyHostToDevice, c->stream));
+    pos += n;
+  }
+  // slots past the restored batch are unused
+  const int Pp = c->dim.Pp;
+  std::vector<PlanState> pad((size_t)(Pp - h.P));
+  for (PlanState& s : pad) {
+    std::memset(&s, 0, sizeof(s));
+    s.status = ST_INACTIVE;
+  }
+  if (!pad.empty())
+    GMCO_HIP(c, hipMemcpyAsync(c->at<PlanState>(c->lay.ps) + h.P, pad.data(), pad.size() * sizeof(PlanState),
+                               hipMemcpyHostToDevice, c->stream));
+  GMCO_HIP(c, hipStreamSynchronize(c->stream));
+  c->dim.S = h.S;
+  c->dim.S_lp = h.S_lp;
+  c->dim.S_tuned = h.S_tuned;
+  c->dim.S_tuned_lp = h.S_tuned_lp;
+  c->P = h.P;
   return GMCO_OK;
 }
 

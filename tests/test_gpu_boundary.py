@@ -1,0 +1,127 @@
+"""The C-ABI's checkpoint calls and error paths on the GPU.
+
+A checkpoint taken after some accepted steps and restored into a fresh
+context continues bitwise like the context it was taken from; every
+documented error code that needs a device (ENOMEM, ESTATE, EINVAL of a
+foreign blob) is returned, not raised inside the library.
+"""
+import numpy as np
+import pytest
+
+import cases
+import oracle as O
+from gpu_common import PARAMS, announce, need_gpu, planner
+
+pytestmark = pytest.mark.gpu
+
+EINVAL, ENOMEM, ESTATE = -1, -2, -4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _fresh(case, dtype="f32", history=10, max_plans=8):
+    from paper_1904_01567_amd import Planner
+    pl = Planner(dtype=dtype, history=history, max_plans=max_plans)
+    pl.load(case, PARAMS)
+    return pl
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f32acc64"])
+def test_checkpoint_restores_bitwise(dtype):
+    announce(f"checkpoint {dtype}")
+    c = cases.case_c1()
+    W = cases.weights_c1()
+    a = planner(c, W, dtype=dtype)
+    # some plans stop by the relative-variation rule, the rest by the cap
+    a.optimize(max_iter=25, eps=2e-4)
+    blob = a.get_state()
+    st = a.metrics()["status"]
+    announce(f"statuses at the checkpoint: {np.bincount(st, minlength=6)}")
+    a.optimize(max_iter=60, eps=2e-4)
+    b = _fresh(c, dtype=dtype)
+    b.set_weights(cases.hidden_weights(3, seed=99))  # replaced by the blob's batch
+    b.set_state(blob)
+    assert b.P == W.shape[0]
+    assert b.get_state() == blob
+    b.optimize(max_iter=60, eps=2e-4)
+    ma, mb = a.metrics(), b.metrics()
+    np.testing.assert_array_equal(b.weights_x(), a.weights_x())
+    for key in ("F_run", "F64", "iterations", "evaluations", "status", "V100_pct"):
+        np.testing.assert_array_equal(mb[key], ma[key], err_msg=key)
+    assert b.get_state() == a.get_state()
+    assert np.any(ma["iterations"] > 25)
+
+
+def test_checkpoint_rejects_foreign_blobs():
+    announce("checkpoint errors")
+    from paper_1904_01567_amd import GmcoError
+    c = cases.case_c1()
+    W = cases.weights_c1()
+    a = planner(c, W)
+    a.optimize(max_iter=3)
+    blob = a.get_state()
+    other = _fresh(c, history=5)  # another history length
+    with pytest.raises(GmcoError) as e:
+        other.set_state(blob)
+    assert e.value.code == EINVAL
+    same = _fresh(c)
+    for bad in (blob[:-8], blob[:40], b"X" + blob[1:]):
+        with pytest.raises(GmcoError) as e:
+            same.set_state(bad)
+        assert e.value.code == EINVAL
+    small = _fresh(c, max_plans=4)  # fewer plan slots than the blob holds
+    with pytest.raises(GmcoError) as e:
+        small.set_state(blob)
+    assert e.value.code == EINVAL
+
+
+def test_state_errors():
+    # calls out of order return ESTATE through the C-ABI
+    announce("ESTATE")
+    import ctypes as C
+    from paper_1904_01567_amd import Planner
+    from paper_1904_01567_amd._binding import gmco_run, gmco_run_info
+    c = cases.small_case()
+    W = np.ascontiguousarray(cases.hidden_weights(2, seed=3))
+    x = np.ones((2, c.K))
+    F = np.empty(2)
+    g = np.empty((2, c.K))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    pl = Planner(max_plans=2)
+    lib, ctx = pl.lib, pl._ctx
+    run = gmco_run(3, 0.0, 1e-4, 0.5, 30, 16, 0, 0, -1, 0)
+    info = gmco_run_info()
+    n = C.c_size_t()
+    blob = C.create_string_buffer(64)
+    assert lib.gmco_set_weights(ctx, 2, dp(W), None) == ESTATE   # before a case
+    assert lib.gmco_set_state(ctx, blob, 64) == ESTATE           # before a case
+    pl.load(c, PARAMS)
+    assert lib.gmco_optimize(ctx, C.byref(run), C.byref(info)) == ESTATE  # before weights
+    assert lib.gmco_evaluate(ctx, dp(x), dp(F), dp(g)) == ESTATE
+    assert lib.gmco_state_bytes(ctx, C.byref(n)) == ESTATE
+    assert lib.gmco_get_state(ctx, blob, 64) == ESTATE
+    assert lib.gmco_get_dwell_times(ctx, dp(g)) == ESTATE
+    assert b"set_weights" in lib.gmco_last_error(ctx)
+    assert lib.gmco_set_weights(ctx, 2, dp(W), None) == 0
+    assert lib.gmco_optimize(ctx, C.byref(run), C.byref(info)) == 0
+    assert info.n_maxiter == 2
+
+
+def test_workspace_too_small_is_enomem():
+    announce("ENOMEM")
+    from paper_1904_01567_amd import GmcoError, Planner
+    c = cases.small_case()
+    pl = Planner(max_plans=4)
+    need = pl.workspace_bytes(c.M, c.K)
+    pl.workspace_bytes = lambda *args: need - 256  # bind one slice short
+    with pytest.raises(GmcoError) as e:
+        pl.load(c, PARAMS)
+    assert e.value.code == ENOMEM
+    del pl.workspace_bytes
+    pl.load(c, PARAMS)  # a big enough workspace works
+    pl.set_weights(cases.hidden_weights(4, seed=1))
+    info = pl.optimize(max_iter=2)
+    assert info["n_maxiter"] == 4
