@@ -88,27 +88,39 @@ def eval_peak_tflops(dtype: str) -> float:
     return PEAK_F32        # f32 and f32chunk64 run both products on FP32 matrix ops
 
 
-def golden_path():
-    return os.path.join(ROOT, "tests", "golden", "c2_reference_optima.json")
+def golden_path(all_plans: bool = True):
+    name = "c2_reference_optima_all.json" if all_plans else "c2_reference_optima.json"
+    return os.path.join(ROOT, "tests", "golden", name)
 
 
 def load_golden():
-    p = golden_path()
+    """The oracle optima of every plan of the batch when stored, else those of
+    the 64-plan sample, as (plan indices, F*, target V100*)."""
+    import numpy as np
+    p = golden_path(True)
+    if os.path.exists(p):
+        with open(p) as fh:
+            g = json.load(fh)
+        return (np.arange(len(g["F"])), np.array(g["F"]),
+                np.array([v[0] for v in g["V100_pct"]]))
+    p = golden_path(False)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
-        return json.load(fh)
+        g = json.load(fh)
+    return (np.array([q["index"] for q in g["plans"]]), np.array([q["F"] for q in g["plans"]]),
+            np.array([q["V100_pct"][0] for q in g["plans"]]))
 
 
 def tolerance_report(metrics, golden):
-    """Compare the device's FP64 objective and target V100 of the sampled
-    plans with the stored oracle optima."""
+    """Compare the device's FP64 objective and target V100 of the plans with
+    the stored oracle optima (every plan of the batch, or the sample)."""
     if golden is None:
         return None
     import numpy as np
-    idx = np.array([q["index"] for q in golden["plans"]])
-    Fs = np.array([q["F"] for q in golden["plans"]])
-    V = np.array([q["V100_pct"][0] for q in golden["plans"]])
+    idx, Fs, V = golden
+    keep = idx < metrics["F64"].shape[0]
+    idx, Fs, V = idx[keep], Fs[keep], V[keep]
     rel = (metrics["F64"][idx] - Fs) / Fs
     dv = np.abs(metrics["V100_pct"][idx, 0] - V)
     return dict(checked_plans=int(idx.size), max_rel_F_excess=float(rel.max()),
@@ -116,28 +128,46 @@ def tolerance_report(metrics, golden):
                 within_tol=int(np.sum((rel <= TOL_F) & (dv <= TOL_V100))))
 
 
-def cpu_baseline(n_plans: int, n_iters: int, iters_full: int):
-    """The FP64 oracle on a bounded sample: n_plans weight vectors of the same
-    case for n_iters iterations, scaled to plans per second at iters_full."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(n_plans: int, max_iter: int, eps: float, n_batch: int = 1000):
+    """The FP64 oracle on a bounded sample of the batch: n_plans of its weight
+    vectors, evenly spread over it, each run to the headline's own stop rule
+    (relative objective variation eps, at most max_iter accepted steps) from
+    the same start.  Plans are independent, so plans per second of the sample
+    is the oracle's rate on the batch."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     import cases
     import oracle as O
     c = cases.case_c2()
-    W = cases.weights_c2()[:n_plans]
+    idx = np.linspace(0, n_batch - 1, n_plans).round().astype(int)
+    W = cases.weights_c2(n_batch)[idx]
     D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
     x0 = O.default_start(D, c.group, c.prescription_gy, n_plans)
     t0 = time.perf_counter()
     r = O.optimize(D, c.group, O.CLASS_SOLUTION_VOLUME, W, x0,
-                   O.LbfgsOptions(max_iter=n_iters))
+                   O.LbfgsOptions(max_iter=max_iter, eps=eps))
     t = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    plans_per_s = n_plans / (t * iters_full / max(1, int(np.max(r["iters"]))))
-    return dict(value=plans_per_s, unit="plans/s", cores=int(threads), kind="oracle",
-                sample=f"{n_plans} plans x {int(np.max(r['iters']))} L-BFGS iterations of the "
-                       f"360-dwell / 20,000-point case in {t:.1f} s (FP64 NumPy, BLAS threads "
-                       f"{threads}), scaled to {iters_full} iterations per plan")
+    return dict(value=n_plans / t, unit="plans/s", cores=int(threads), kind="oracle",
+                host_cpu=host_cpu_model(), host_logical_cpus=os.cpu_count(),
+                sample=f"{n_plans} of the {n_batch} weight vectors (every "
+                       f"{max(1, n_batch // n_plans)}th) of the 360-dwell / 20,000-point case, each "
+                       f"run to its own stop (relative objective variation {eps:g}, at most "
+                       f"{max_iter} steps; {int(np.sum(r['iters']))} accepted steps in all, "
+                       f"median {int(np.median(r['iters']))}) in {t:.1f} s (FP64 NumPy, BLAS "
+                       f"threads {threads})")
 
 
 def eval_traffic(dtype: str, plans: int):
@@ -236,14 +266,21 @@ def surface_volume(args) -> int:
 
 
 def warm_start_compare(args) -> int:
-    """Warm-started BF16 form against plain FP32 L-BFGS at equal objective
-    accuracy: train the network on the method's own plans for a few cases of
-    the paper-scale layout, then on held-out cases time how long each form
-    takes until all 1,000 plans are within a relative target of a long
-    FP64-accumulated reference run."""
+    """The learned warm start at the scale of its configuration: train the
+    network on the method's own plans for --train-cases cases (1,000 plans
+    each) of the paper-scale layout, then on --heldout held-out cases time
+      * the headline arithmetic (the default ladder and stop rule) from the
+        uniform start and from the learned start (its set-up counted), until
+        every plan stops, with the number of plans within the headline
+        tolerance of a long FP64-accumulated reference run;
+      * plain FP32 L-BFGS from the uniform start against the learned start
+        with BF16 then FP32 steps, time until all plans are within looser
+        relative targets (first --grid-cases held-out cases)."""
     import numpy as np
+    import torch
 
     import cases
+    from paper_1904_01567_amd import Planner, class_solution
     from paper_1904_01567_amd import warmstart as ws
     sizes = [68, 256, 256, 256, 360]
     stages = [ws.Stage("bf16", 150), ws.Stage("f32acc64", 1000)]
@@ -253,26 +290,68 @@ def warm_start_compare(args) -> int:
         X, Y = ws.labels_for_case(cases.case_learned(i), cases.weights_learned(i, args.plans), stages)
         Xs.append(X)
         Ys.append(Y)
+        if (i + 1) % 25 == 0:
+            print(f"# labels {i + 1}/{args.train_cases}", file=sys.stderr, flush=True)
     X, Y = np.concatenate(Xs), np.concatenate(Ys)
+    del Xs, Ys
     t_labels = time.perf_counter() - t0
     t0 = time.perf_counter()
     net, losses = ws.train_network(X, Y, sizes, 30, 1024, 1e-3,
                                    cases.mlp_init(sizes, seed=7).astype(np.float32),
                                    lambda n, s, b, e: cases.batch_order(n, s, b, seed=100 + e))
     t_train = time.perf_counter() - t0
+    n_samples = int(X.shape[0])
+    del X, Y
+    print(f"# trained on {n_samples} plans: loss {losses[0]:.4g} -> {losses[-1]:.4g}",
+          file=sys.stderr, flush=True)
+    ladder = [ws.Stage(d, int(n)) for d, n in (st.split(":") for st in DEFAULT_LADDER.split(","))]
     targets = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]
-    grid = [10, 20, 40, 60, 80, 120, 160, 240, 320, 480, 640, 960, 1280]
+    grid = [10, 20, 40, 80, 160, 320, 640, 1280]
     rows = []
     for h in range(args.heldout):
         idx = 10_000 + h
-        r = ws.time_to_accuracy(net, cases.case_learned(idx), cases.weights_learned(idx, args.plans),
-                                targets, grid, floors=(1e-3, 0.1, 0.3))
-        rows.append({"case": idx, **{k: v["time_to_target"] for k, v in r.items()}})
-        print(f"# held-out {h + 1}/{args.heldout}", file=sys.stderr, flush=True)
-    print(json.dumps({"train_cases": args.train_cases, "plans": args.plans, "label_s": t_labels,
-                      "train_s": t_train, "loss": [losses[0], losses[-1]],
-                      "reference": "f32acc64, 2000 steps, cold start", "targets": targets,
-                      "rows": rows}), flush=True)
+        case, W = cases.case_learned(idx), cases.weights_learned(idx, args.plans)
+        pl = Planner(dtype="bf16", max_plans=args.plans)
+        pl.load(case, class_solution.VOLUME)
+        pl.set_weights(W)
+        pl.optimize(max_iter=6000, dtype="f32acc64")
+        F_ref = pl.metrics()["F64"]
+        row = {"case": idx}
+        for form in ("cold", "warm"):
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            if form == "cold":
+                pl.set_weights(W)
+            else:
+                use = pl.set_weights_learned(net, W, ws.X_FLOOR)
+                row["learned_start_kept"] = int(use.sum())
+            for k, st in enumerate(ladder):
+                pl.optimize(max_iter=st.max_iter, dtype=st.dtype, eps=DEFAULT_EPS, resume_stopped=k > 0)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t_start)
+            rel = pl.metrics()["F64"] / F_ref - 1.0
+            row[form] = {"ms": ms, "within_tol": int(np.sum(rel <= TOL_F)),
+                         "max_rel_excess": float(rel.max())}
+        pl.close()
+        if h < args.grid_cases:
+            r = ws.time_to_accuracy(net, case, W, targets, grid, F_ref=F_ref, floors=(1e-3, 0.1))
+            row["fp32_targets"] = {k: v["time_to_target"] for k, v in r.items()}
+        rows.append(row)
+        print(f"# held-out {h + 1}/{args.heldout}: cold {row['cold']['ms']:.0f} ms "
+              f"({row['cold']['within_tol']}), warm {row['warm']['ms']:.0f} ms ({row['warm']['within_tol']}), "
+              f"learned start kept {row['learned_start_kept']}", file=sys.stderr, flush=True)
+    med = lambda key, f: float(np.median([r[key][f] for r in rows]))
+    print(json.dumps({
+        "train_cases": args.train_cases, "plans": args.plans, "samples": n_samples,
+        "label_s": t_labels, "train_s": t_train, "loss": [losses[0], losses[-1]],
+        "heldout": args.heldout,
+        "headline_form": {"ladder": DEFAULT_LADDER, "eps": DEFAULT_EPS, "tol_rel_F": TOL_F,
+                          "reference": "f32acc64, 6000 steps, uniform start",
+                          "median_ms": {"cold": med("cold", "ms"), "warm": med("warm", "ms")},
+                          "cases_all_within_tol": {f: int(sum(r[f]["within_tol"] == args.plans for r in rows))
+                                                   for f in ("cold", "warm")},
+                          "median_learned_start_kept": float(np.median([r["learned_start_kept"] for r in rows]))},
+        "targets": targets, "rows": rows}), flush=True)
     return 0
 
 
@@ -315,10 +394,11 @@ def precision_report(args) -> int:
 
     import cases
     from paper_1904_01567_amd import Planner, class_solution
-    golden = load_golden()
-    if golden is None:
+    if not os.path.exists(golden_path(False)):
         print(json.dumps({"error": "no reference optima"}))
         return 2
+    with open(golden_path(False)) as fh:
+        golden = json.load(fh)
     idx = np.array([q["index"] for q in golden["plans"]])
     Fs = np.array([q["F"] for q in golden["plans"]])
     V = np.array([q["V100_pct"][0] for q in golden["plans"]])
@@ -443,8 +523,8 @@ def main(argv=None) -> int:
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-plans", type=int, default=32)
-    ap.add_argument("--cpu-iters", type=int, default=150)
+    ap.add_argument("--cpu-plans", type=int, default=16,
+                    help="plans of the oracle's host timing, spread over the batch")
     ap.add_argument("--calibrate", type=str, default=None,
                     help="comma-separated iteration counts: print the tolerance report at each")
     ap.add_argument("--batched", type=int, default=0,
@@ -465,15 +545,17 @@ def main(argv=None) -> int:
                     help="8-group objective with a separate DVH point set (paper-scale layout)")
     ap.add_argument("--warm-start-compare", action="store_true",
                     help="warm-started BF16 form vs plain FP32 L-BFGS, time to equal accuracy")
-    ap.add_argument("--train-cases", type=int, default=20)
-    ap.add_argument("--heldout", type=int, default=3)
+    ap.add_argument("--train-cases", type=int, default=500)
+    ap.add_argument("--heldout", type=int, default=50)
+    ap.add_argument("--grid-cases", type=int, default=10,
+                    help="held-out cases that also time the FP32 forms against looser targets")
     ap.add_argument("--precision-report", action="store_true",
                     help="per arithmetic: objective, target V100 and OAR D10 errors of the "
                          "sampled plans against the FP64 oracle optima")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB buffer once (reference for HBM byte counters)")
     ap.add_argument("--cpu-only", action="store_true",
-                    help="only the oracle's host timing (--cpu-plans x --cpu-iters), no GPU")
+                    help="only the oracle's host timing (--cpu-plans plans to the stop rule), no GPU")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="BLAS threads of the host timing (0: all host cores)")
     args = ap.parse_args(argv)
@@ -488,10 +570,9 @@ def main(argv=None) -> int:
         import numpy  # noqa: F401  (BLAS loaded, so that the limit reaches it)
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=args.cpu_threads or None):
-            r = cpu_baseline(args.cpu_plans, args.cpu_iters, args.iters or 2000)
-        print(json.dumps({"cpu_baseline": r, "s_per_plan": 1.0 / r["value"],
-                          "host_cpu": platform.processor() or platform.machine(),
-                          "host_cores": os.cpu_count()}), flush=True)
+            r = cpu_baseline(args.cpu_plans, args.iters or 2000,
+                             DEFAULT_EPS if args.eps is None else args.eps)
+        print(json.dumps({"cpu_baseline": r, "s_per_plan": 1.0 / r["value"]}), flush=True)
         return 0
 
     import numpy as np
@@ -650,7 +731,7 @@ def main(argv=None) -> int:
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_plans, args.cpu_iters, iters)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_plans, iters, run_eps, args.plans)
     print(json.dumps(out), flush=True)
     return 0
 

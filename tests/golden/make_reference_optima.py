@@ -9,12 +9,14 @@ Calls only the oracle and the seeded case generator.  Two outputs:
 * tests/golden/c2_reference_optima_all.json (--all): every one of the 1,000
   plans, compactly (F*, per-organ V100 / D10 / V75 and individual objectives,
   iterations, status), computed by --workers processes that each run the
-  oracle on a contiguous share of the plans with one BLAS thread.  Plans are
-  independent (Sec. 2.2.1), so the share a plan is run in does not change its
-  optimum.
+  oracle on shares of --share consecutive plans with one BLAS thread.  Each
+  finished share is written to tests/golden/c2_optima_parts/ at once, and a
+  restarted run skips the shares already there; the merged file is written
+  when every share is done.  Plans are independent (Sec. 2.2.1), so the share
+  a plan is run in does not change its optimum.
 
     python tests/golden/make_reference_optima.py [--max-iter 20000]
-    python tests/golden/make_reference_optima.py --all --workers 8
+    python tests/golden/make_reference_optima.py --all --workers 6
 """
 import argparse
 import json
@@ -55,38 +57,62 @@ def _run(plans, max_iter):
     return r, m
 
 
+PARTS = os.path.join(HERE, "c2_optima_parts")
+KEYS = ("F", "iters", "status", "V100_pct", "D10_pct", "V75_cc", "f_organ")
+
+
+def _part_path(lo, hi):
+    return os.path.join(PARTS, f"plans_{lo:04d}_{hi - 1:04d}.json")
+
+
 def _share(job):
-    """One worker: the oracle on plans lo..hi-1 with one BLAS thread."""
+    """One worker: the oracle on plans lo..hi-1 with one BLAS thread; the
+    share is written to its part file when done."""
     lo, hi, max_iter = job
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.time()
         r, m = _run(list(range(lo, hi)), max_iter)
-    print(f"plans {lo}-{hi - 1} done in {time.time() - t0:.0f} s", flush=True)
-    return dict(F=r["F"].tolist(), iters=r["iters"].tolist(), status=r["status"].tolist(),
+    part = dict(lo=lo, hi=hi, max_iter=max_iter, eps=EPS, seconds=time.time() - t0,
+                F=r["F"].tolist(), iters=r["iters"].tolist(), status=r["status"].tolist(),
                 V100_pct=[q["V100_pct"].tolist() for q in m],
                 D10_pct=[q["D10_pct"].tolist() for q in m],
                 V75_cc=[q["V75_cc"].tolist() for q in m],
                 f_organ=[q["f_organ"].tolist() for q in m])
+    tmp = _part_path(lo, hi) + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(part, fh, separators=(",", ":"))
+    os.replace(tmp, _part_path(lo, hi))
+    print(f"plans {lo}-{hi - 1} done in {part['seconds']:.0f} s", flush=True)
+    return lo
 
 
 def write_all(args):
     import multiprocessing as mp
     n = 1000
-    bounds = np.linspace(0, n, args.workers + 1).astype(int)
-    jobs = [(int(a), int(b), args.max_iter) for a, b in zip(bounds[:-1], bounds[1:])]
+    os.makedirs(PARTS, exist_ok=True)
+    jobs = [(lo, min(lo + args.share, n), args.max_iter) for lo in range(0, n, args.share)]
+    todo = [j for j in jobs if not os.path.exists(_part_path(j[0], j[1]))]
     t0 = time.time()
-    with mp.get_context("spawn").Pool(args.workers) as pool:
-        parts = pool.map(_share, jobs)
+    if todo:
+        with mp.get_context("spawn").Pool(args.workers) as pool:
+            for _ in pool.imap_unordered(_share, todo):
+                pass
+    parts = []
+    for lo, hi, _ in jobs:
+        with open(_part_path(lo, hi)) as fh:
+            q = json.load(fh)
+        assert q["max_iter"] == args.max_iter and q["eps"] == EPS, "part of another run"
+        parts.append(q)
     out = dict(workload=WORKLOAD,
                options=dict(m=10, max_iter=args.max_iter, eps=EPS, c1=1e-4, beta=0.5, max_ls=30),
-               seconds=time.time() - t0, workers=args.workers, plans=n)
-    for key in ("F", "iters", "status", "V100_pct", "D10_pct", "V75_cc", "f_organ"):
-        out[key] = [v for p in parts for v in p[key]]
+               seconds=sum(q["seconds"] for q in parts), workers=args.workers, plans=n)
+    for key in KEYS:
+        out[key] = [v for q in parts for v in q[key]]
     path = args.out or os.path.join(HERE, "c2_reference_optima_all.json")
     with open(path, "w") as fh:
         json.dump(out, fh, separators=(",", ":"))
-    print(f"wrote {path} in {out['seconds']:.0f} s")
+    print(f"wrote {path}: {out['seconds']:.0f} worker-seconds, {time.time() - t0:.0f} s wall")
 
 
 def write_sample(args):
@@ -115,7 +141,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--all", action="store_true", help="every plan of the batch, compact form")
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=6)
+    ap.add_argument("--share", type=int, default=25, help="plans per worker task (--all)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     if args.all:

@@ -17,13 +17,15 @@ def test_more_than_one_gpu_is_refused(capsys):
 
 
 def test_host_oracle_timing_line(capsys):
-    # one plan, three L-BFGS iterations of the paper-scale case, one BLAS thread
+    # one plan of the paper-scale case run to its own stop, here a cap of three
+    # accepted steps, with one BLAS thread
     assert bench.main(["--cpu-only", "--cpu-threads", "1", "--cpu-plans", "1",
-                       "--cpu-iters", "3", "--iters", "2000"]) == 0
+                       "--iters", "3"]) == 0
     d = _last_json(capsys)
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["unit"] == "plans/s"
     assert cb["cores"] == 1
     assert cb["value"] > 0.0
     assert abs(d["s_per_plan"] * cb["value"] - 1.0) < 1e-12
-    assert "scaled to 2000 iterations" in cb["sample"]
+    assert "at most 3 steps; 3 accepted steps in all" in cb["sample"]
+    assert cb["host_cpu"]
