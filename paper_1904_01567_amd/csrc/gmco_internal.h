@@ -181,6 +181,19 @@ hipError_t launch_metrics_final(const MetricsArgs& m, hipStream_t st);
 
 hipError_t launch_select(const gmco_plan_metrics* m, int P, int G, const gmco_select_opts& o, int* cls,
                          int* meets_tu, int* nd, int* out, hipStream_t st);
+// Network of the learned warm start (defined with its kernels).
+int mlp_inputs(const gmco_mlp* m);
+int mlp_outputs(const gmco_mlp* m);
+int mlp_device(const gmco_mlp* m);
+hipError_t mlp_forward_device(gmco_mlp* m, int B, const float* X, float* Y, hipStream_t st);
+// Learned start: network inputs per plan (hidden weights, then the case
+// features), the floored start x0 = max(y, floor) sqrt(t_bar), and the
+// per-plan choice between it and the uniform start.
+hipError_t launch_learned_inputs(const double* W64, const float* feat, int P, int O, float* X, hipStream_t st);
+hipError_t launch_learned_start(const float* Y, int P, int Pp, int K, int Kp, const double* t_bar, double floor,
+                                float* xe, hipStream_t st);
+hipError_t launch_pick_start(const double* F_warm, const double* F_uniform, const float* xe, int P, int Kp,
+                             float* x, float* xt, int* n_warm, int* use_warm, hipStream_t st);
 hipError_t launch_features(const double* dwell, const double* pts, const int* perm, const int* goff,
                            const int* gcnt, int K, int G, unsigned* hist, float* out, hipStream_t st);
 

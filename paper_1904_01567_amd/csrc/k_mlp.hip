@@ -243,17 +243,19 @@ hipError_t gemm(hipStream_t st, const float* A, long sai, long sak, const float*
 
 int layers(const gmco_mlp* m) { return (int)m->sizes.size() - 1; }
 
-// forward over act[0] (B rows): act[k+1] = relu?(act[k] W_k^T + b_k)
-hipError_t forward(gmco_mlp* m, int B) {
+// forward over act[0] (B rows): act[k+1] = relu?(act[k] W_k^T + b_k), on
+// stream st (the network's own unless a caller's)
+hipError_t forward(gmco_mlp* m, int B, hipStream_t st) {
   const int L = layers(m);
   for (int k = 0; k < L; ++k) {
     const int in = m->sizes[k], out = m->sizes[k + 1];
-    hipError_t e = gemm(m->stream, m->act[k], in, 1, m->p + m->woff[k], 1, in, m->act[k + 1], out,
+    hipError_t e = gemm(st, m->act[k], in, 1, m->p + m->woff[k], 1, in, m->act[k + 1], out,
                         m->p + m->boff[k], B, out, in, k < L - 1);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
+hipError_t forward(gmco_mlp* m, int B) { return forward(m, B, m->stream); }
 
 // backward from the targets in m->y; gradients into m->g, loss into *m->loss
 hipError_t backward(gmco_mlp* m, int B) {
@@ -489,6 +491,29 @@ int gmco_mlp_predict(gmco_mlp* m, int B, const float* X, float* Y) {
 }  // extern "C"
 
 namespace gmco {
+int mlp_inputs(const gmco_mlp* m) { return m->sizes.front(); }
+int mlp_outputs(const gmco_mlp* m) { return m->sizes.back(); }
+int mlp_device(const gmco_mlp* m) { return m->device; }
+
+// The network on B rows held in device memory (X: B x n_in, Y: B x n_out),
+// in chunks of max_batch rows, all on stream st.  The network's activation
+// buffers are used, so st must be ordered with the network's other work.
+hipError_t mlp_forward_device(gmco_mlp* m, int B, const float* X, float* Y, hipStream_t st) {
+  const int L = layers(m);
+  for (int b0 = 0; b0 < B; b0 += m->max_batch) {
+    const int nb = std::min(m->max_batch, B - b0);
+    hipError_t e = hipMemcpyAsync(m->act[0], X + (size_t)b0 * m->sizes[0], (size_t)nb * m->sizes[0] * 4,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    e = forward(m, nb, st);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(Y + (size_t)b0 * m->sizes[L], m->act[L], (size_t)nb * m->sizes[L] * 4,
+                       hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_features(const double* dwell, const double* pts, const int* perm, const int* goff,
                            const int* gcnt, int K, int G, unsigned* hist, float* out, hipStream_t st) {
   hipError_t e = hipMemsetAsync(hist, 0, (size_t)G * 16 * 4, st);

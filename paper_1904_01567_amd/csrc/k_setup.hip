@@ -179,7 +179,73 @@ __global__ void k_x_to_device(const double* __restrict__ xin, int P, int K, int 
     xe[(size_t)p * Kp + l] = (p < P && l < K) ? (float)xin[(size_t)p * K + l] : 0.f;
 }
 
+// Network inputs of the learned start: row p is the plan's hidden weights
+// (one per organ, as given) followed by the case features.
+__global__ void k_learned_inputs(const double* __restrict__ W64, const float* __restrict__ feat, int O,
+                                 float* __restrict__ X) {
+  const int p = blockIdx.x;
+  const int n_in = O + 16 * O;
+  for (int i = threadIdx.x; i < n_in; i += blockDim.x)
+    X[(size_t)p * n_in + i] = i < O ? (float)W64[(size_t)p * kGmax + i] : feat[i - O];
+}
+
+// Start dwell weights from the network's output y (normalised by the uniform
+// start): x0 = max(y, floor) sqrt(t_bar); a non-finite y stays non-finite, so
+// that the plan's start objective is too and the plan falls back.
+__global__ void k_learned_start(const float* __restrict__ Y, int K, int Kp, const double* __restrict__ t_bar,
+                                float floor, float* __restrict__ xe) {
+  const int p = blockIdx.x;
+  const float sc = (float)sqrt(*t_bar);
+  for (int l = threadIdx.x; l < Kp; l += blockDim.x) {
+    float v = 0.f;
+    if (l < K) {
+      const float y = Y[(size_t)p * K + l];
+      v = (isfinite(y) ? fmaxf(y, floor) : y) * sc;
+    }
+    xe[(size_t)p * Kp + l] = v;
+  }
+}
+
+// Per plan: keep the learned start only where its objective is finite and
+// below the uniform start's (plain L-BFGS from the uniform start is the
+// fallback).  The chosen point becomes the plan's start (status INIT).
+__global__ void k_pick_start(const double* __restrict__ Fw, const double* __restrict__ Fu,
+                             const float* __restrict__ xe, int Kp, float* __restrict__ x,
+                             float* __restrict__ xt, int* __restrict__ n_warm, int* __restrict__ use_warm) {
+  const int p = blockIdx.x;
+  const double fw = Fw[p];
+  const bool warm = isfinite(fw) && fw < Fu[p];
+  if (threadIdx.x == 0) {
+    use_warm[p] = warm ? 1 : 0;
+    if (warm) atomicAdd(n_warm, 1);
+  }
+  if (!warm) return;
+  for (int l = threadIdx.x; l < Kp; l += blockDim.x) {
+    const float v = xe[(size_t)p * Kp + l];
+    x[(size_t)p * Kp + l] = v;
+    xt[(size_t)p * Kp + l] = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_learned_inputs(const double* W64, const float* feat, int P, int O, float* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_learned_inputs, dim3(P), dim3(128), 0, st, W64, feat, O, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_start(const float* Y, int P, int Pp, int K, int Kp, const double* t_bar, double floor,
+                                float* xe, hipStream_t st) {
+  (void)Pp;
+  hipLaunchKernelGGL(k_learned_start, dim3(P), dim3(128), 0, st, Y, K, Kp, t_bar, (float)floor, xe);
+  return hipGetLastError();
+}
+
+hipError_t launch_pick_start(const double* F_warm, const double* F_uniform, const float* xe, int P, int Kp,
+                             float* x, float* xt, int* n_warm, int* use_warm, hipStream_t st) {
+  hipLaunchKernelGGL(k_pick_start, dim3(P), dim3(128), 0, st, F_warm, F_uniform, xe, Kp, x, xt, n_warm, use_warm);
+  return hipGetLastError();
+}
 
 hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
                             const int* perm, int M, int K, int Mp, int Kp, double* D64,

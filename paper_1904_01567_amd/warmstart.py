@@ -5,11 +5,16 @@ batched L-BFGS refines from there and remains the fallback.
 Inputs per plan: the n_groups hidden weights followed by the case features
 (n_groups x 16 distance histograms, computed on the GPU).  Output per dwell:
 x_hat = |x*| / sqrt(t_bar), the method's converged dwell weight normalised by
-the case's uniform start; the start is t0 = (max(x_hat, floor) sqrt(t_bar))^2
-because x = 0 is a fixed point of the x^2 substitution.
+the case's uniform start; the start is x0 = max(x_hat, floor) sqrt(t_bar)
+because x = 0 is a fixed point of the x^2 substitution.  The library builds
+the inputs, runs the network, floors and scales its output and keeps, per
+plan, the learned start only where its objective is below the uniform
+start's (gmco_set_weights_learned): plain L-BFGS from the uniform start is
+the fallback.
 
 Every numerical step runs in the library (optimiser, features, network
-training and inference); this module only moves arrays between the calls.
+training and inference, the start and its fallback); this module only moves
+arrays between the calls.
 """
 from __future__ import annotations
 
@@ -59,12 +64,15 @@ def labels_for_case(case, W, stages, dtype_ctx="bf16", params=None):
     return X, xh.astype(np.float32)
 
 
-def warm_start_times(net: Network, pl: Planner, W: np.ndarray, floor: float = X_FLOOR) -> np.ndarray:
-    """t0 for a weight batch on the loaded case, from the network; predicted
-    dwell weights are floored at `floor` (x = 0 is a fixed point)."""
-    feats = pl.case_features()
-    xh = net.predict(plan_inputs(W, feats)).astype(np.float64)
-    return (np.maximum(xh, floor) ** 2) * pl.start_time()
+def learned_start(net: Network, pl: Planner, W: np.ndarray, floor: float = X_FLOOR):
+    """Set the weight batch with the learned start on the loaded case; returns
+    (per-plan flag: learned start kept, host ms of the call: features,
+    network and the two start evaluations)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    use = pl.set_weights_learned(net, W, floor)
+    return use, 1e3 * (time.perf_counter() - t0)
 
 
 def train_network(X, Y, sizes, epochs: int, batch: int, lr: float, init_params, order_fn,
@@ -90,61 +98,71 @@ def compare_cold_warm(net: Network, case, W, checkpoints, dtype_ctx="bf16", para
     pl.load(case, params)
     out = {}
     for name in ("cold", "warm"):
-        t0 = None if name == "cold" else warm_start_times(net, pl, W)
-        pl.set_weights(W, t0)
-        F = {0: pl.metrics()["F64"]}
         ms = 0.0
+        if name == "cold":
+            pl.set_weights(W)
+        else:
+            use, ms = learned_start(net, pl, W)
+        F = {0: pl.metrics()["F64"]}
         for n in checkpoints:
             info = pl.optimize(max_iter=n, dtype=final_dtype)
             ms += info["device_ms"]
             F[n] = pl.metrics()["F64"]
         out[name] = dict(F=F, device_ms=ms)
+        if name == "warm":
+            out[name]["learned_start_kept"] = int(use.sum())
     pl.close()
     return out
 
 
-def _timed_run(pl: Planner, W, t0, stages):
-    """Device ms of the stages (a ladder) from a fresh start, and F_64 after."""
-    pl.set_weights(W, t0)
+def _timed_run(pl: Planner, W, start, stages, net=None):
+    """ms of the stages (a ladder) from a fresh start, and F_64 after.  start
+    None is the uniform start; a float is the floor of the learned start,
+    whose set-up (features, network, start evaluations) is counted."""
     ms = 0.0
+    if start is None:
+        pl.set_weights(W)
+    else:
+        _, ms = learned_start(net, pl, W, start)
     for k, st in enumerate(stages):
         ms += pl.optimize(max_iter=st.max_iter, dtype=st.dtype, resume_stopped=k > 0)["device_ms"]
     return ms, pl.metrics()["F64"]
 
 
 def time_to_accuracy(net: Network, case, W, targets, grid, dtype_ctx="bf16", params=None,
-                     ref_iters=2000, warm_bf16_steps=100, floors=(X_FLOOR,)):
+                     ref_iters=2000, warm_bf16_steps=100, floors=(X_FLOOR,), F_ref=None):
     """Time for all plans of the batch to come within each relative target of
-    a reference objective (a long FP64-accumulated cold run), for
+    a reference objective (F_ref, else a long FP64-accumulated cold run), for
       cold: plain FP32 L-BFGS from the uniform start, n steps;
-      warm: the network's start, BF16 for the first warm_bf16_steps steps,
-            then FP32 to n steps.
+      warm: the learned start (with its per-plan fallback), BF16 for the
+            first warm_bf16_steps steps, then FP32 to n steps; its time
+            includes the learned start's set-up.
     n runs over `grid`; the first n at which every plan meets the target gives
-    the time (device ms of a fresh run of n steps).  None when no n does.
-    One warm form per floor of the predicted dwell weights."""
+    the time (ms of a fresh run of n steps).  None when no n does.  One warm
+    form per floor of the predicted dwell weights."""
     params = class_solution.VOLUME if params is None else params
     pl = Planner(dtype=dtype_ctx, max_plans=W.shape[0])
     pl.load(case, params)
-    _, F_ref = _timed_run(pl, W, None, [Stage("f32acc64", ref_iters)])
+    if F_ref is None:
+        _, F_ref = _timed_run(pl, W, None, [Stage("f32acc64", ref_iters)])
     forms = {"cold_f32": lambda n: (None, [Stage("f32", n)])}
     for fl in floors:
-        t_warm = warm_start_times(net, pl, W, fl)
         forms[f"warm_bf16_floor{fl:g}"] = (
-            lambda n, t_warm=t_warm: (t_warm, [Stage("bf16", min(n, warm_bf16_steps))] +
-                                      ([Stage("f32", n)] if n > warm_bf16_steps else [])))
+            lambda n, fl=fl: (fl, [Stage("bf16", min(n, warm_bf16_steps))] +
+                              ([Stage("f32", n)] if n > warm_bf16_steps else [])))
     out = {}
     for name, form in forms.items():
         res = {}
         curve = []
         for n in grid:
-            t0, stages = form(n)
-            ms, F = _timed_run(pl, W, t0, stages)
+            start, stages = form(n)
+            ms, F = _timed_run(pl, W, start, stages, net)
             worst = float(np.max(F / F_ref - 1.0))
             curve.append((n, ms, worst))
         for a in targets:
             hit = next(((n, ms) for n, ms, w in curve if w <= a), None)
-            res[str(a)] = None if hit is None else {"steps": hit[0], "device_ms": hit[1]}
-        out[name] = dict(time_to_target=res, curve=[{"steps": n, "device_ms": ms, "worst_rel_excess": w}
+            res[str(a)] = None if hit is None else {"steps": hit[0], "ms": hit[1]}
+        out[name] = dict(time_to_target=res, curve=[{"steps": n, "ms": ms, "worst_rel_excess": w}
                                                     for n, ms, w in curve])
     pl.close()
     return out

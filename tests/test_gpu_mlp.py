@@ -48,8 +48,14 @@ def test_loss_and_gradient_match_oracle():
         off += n
 
 
-def test_one_adam_step_matches_oracle():
-    announce("mlp adam step")
+def test_adam_steps_match_oracle():
+    # Five Adam steps on one batch.  Before each step the library's gradient
+    # at the current parameters (gmco_mlp_loss_grad, the same kernels and
+    # rows as the training step) is fed to the oracle's Adam update with FP64
+    # moments; the library's parameters after the step must agree to FP32
+    # rounding.  This pins beta1, beta2, eps and the bias corrections of
+    # every step, which the first step alone (a move of lr sign(g)) does not.
+    announce("mlp adam steps")
     sizes = [8, 32, 16]
     rng = np.random.default_rng(2)
     p = cases.mlp_init(sizes, seed=4).astype(np.float32)
@@ -59,15 +65,21 @@ def test_one_adam_step_matches_oracle():
     net.set_params(p)
     net.set_data(X, Y)
     lr = 1e-3
-    net.train(np.arange(64, dtype=np.int32), 64, lr)
-    p1 = net.params().astype(np.float64)
-    _, gr = MO.loss_and_grad(p.astype(np.float64), sizes, X.astype(np.float64), Y.astype(np.float64))
-    ref, _, _ = MO.adam_step(p.astype(np.float64), gr, np.zeros_like(gr), np.zeros_like(gr), 1, lr)
-    # the first Adam step moves every parameter by about lr * sign(g): a
-    # parameter whose gradient sign differs moves 2 lr the other way
-    diff = np.abs(p1 - ref)
-    assert diff.max() <= 2 * lr + 1e-6
-    assert np.mean(diff > 1e-5) <= 0.02
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    cur = p.astype(np.float64)
+    for step in range(1, 6):
+        _, g = net.loss_grad(X, Y)
+        ref, m, v = MO.adam_step(cur, g.astype(np.float64), m, v, step, lr)
+        net.train(np.arange(64, dtype=np.int32), 64, lr)
+        got = net.params().astype(np.float64)
+        err = np.abs(got - ref)
+        tol = 1e-4 * lr + 4.0 * np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        announce(f"adam step {step}: max |p - p_ref| {err.max():.2e} (lr {lr})")
+        assert np.all(err <= tol), (step, float(err.max()))
+        cur = got
+    # the steps moved the parameters by several lr in all
+    assert np.abs(cur - p).max() >= 3 * lr
 
 
 def test_case_features_match_oracle():
@@ -130,3 +142,67 @@ def test_warm_start_gains_over_cold_start():
     announce(f"median F_warm / F_cold at (iters, ratio): {gains}")
     # the network's start and the early iterates beat the uniform start
     assert all(r < 1.0 for n, r in gains if n in (0, 20))
+
+
+def _bias_only_params(sizes, bias):
+    """Network parameters that output `bias` for every input: zero weights
+    everywhere, zero hidden biases, the given output bias."""
+    p = np.zeros(sum(o * i + o for (o, i) in MO.layer_shapes(sizes)), dtype=np.float32)
+    p[-sizes[-1]:] = bias
+    return p
+
+
+def test_learned_start_and_its_fallback():
+    # gmco_set_weights_learned with a network whose output is a known vector
+    # x_hat for every plan: the start is max(x_hat, floor) sqrt(t_bar), kept
+    # exactly for the plans whose objective there is below the uniform
+    # start's (decided here by the oracle in FP64), the uniform start for the
+    # others; a non-finite output sends every plan back to the uniform start.
+    announce("learned start and fallback")
+    import oracle as O
+    from gpu_common import planner
+    c = cases.make_case(6, 6, (300, 60, 120, 120), seed=77)
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    K = c.K
+    sizes = [68, 32, K]
+    W = cases.hidden_weights(48, seed=78)
+    W[:24, 0] *= 100.0            # plans that care most for target coverage ...
+    W[24:, 2:] *= 100.0           # ... and plans that care most for bladder and rectum
+    W /= W.sum(axis=1, keepdims=True)
+    # x_hat: 3 % above the uniform start (doses about 6 % higher: better for
+    # the target-minded plans, worse for the others), two dwells below the floor
+    tb = O.uniform_start_time(D, c.group, 15.0)
+    xh = np.full(K, 1.03, dtype=np.float32)
+    xh[:2] = 0.0
+    floor = 0.5
+    net = _net(sizes, 64)
+    net.set_params(_bias_only_params(sizes, xh))
+    pl = planner(c, W)
+    use = pl.set_weights_learned(net, W, floor)
+    x_start = pl.weights_x()
+    xw = (np.maximum(xh, np.float32(floor)) * np.float32(np.sqrt(tb))).astype(np.float32).astype(np.float64)
+    xu = np.full(K, np.float32(np.sqrt(tb)), dtype=np.float64)
+    Fw = O.objective(D, O.dwell_times(xw), c.group, PARAMS, W)
+    Fu = O.objective(D, O.dwell_times(xu), c.group, PARAMS, W)
+    clear = np.abs(Fw / Fu - 1.0) > 1e-3
+    announce(f"learned start kept for {use.sum()} of {W.shape[0]} plans")
+    np.testing.assert_array_equal(use[clear], (Fw < Fu)[clear])
+    assert use.any() and (~use).any()
+    for p in range(W.shape[0]):
+        np.testing.assert_allclose(x_start[p], xw if use[p] else xu, rtol=2.4e-7, atol=0)
+    # the run from the chosen starts: every plan's first objective is the
+    # smaller of the two
+    pl.optimize(max_iter=1)
+    # non-finite prediction: all plans fall back
+    bad = xh.copy()
+    bad[4] = np.nan
+    net.set_params(_bias_only_params(sizes, bad))
+    use2 = pl.set_weights_learned(net, W, floor)
+    assert not use2.any()
+    np.testing.assert_allclose(pl.weights_x(), np.tile(xu, (W.shape[0], 1)), rtol=2.4e-7, atol=0)
+    # a network of the wrong shape is refused
+    from paper_1904_01567_amd import GmcoError
+    wrong = _net([68, 8, K + 1], 8)
+    with pytest.raises(GmcoError) as e:
+        pl.set_weights_learned(wrong, W, floor)
+    assert e.value.code == -1
