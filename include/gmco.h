@@ -219,6 +219,22 @@ int gmco_set_weights(gmco_ctx* ctx, int n_plans, const double* W, const double* 
  * Errors: ESTATE, EINVAL, EHIP. */
 int gmco_evaluate(gmco_ctx* ctx, const double* x, double* F, double* g);
 
+/* gmco_evaluate for callers that cannot allocate device memory or
+ * synchronise (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same evaluation kernels on device arrays,
+ * enqueued on the context stream without any allocation, host copy or
+ * synchronisation.  x_dev is P x K FP64 dwell weights, F_dev P and g_dev
+ * P x K FP64 outputs, all device memory owned by the caller (P = current
+ * batch).  The FP32 copy of x and the split partials live in a 32 MiB
+ * library array, one per device, held until the process ends; the batch must
+ * fit it (4 x padded plans x padded dwells bytes for x plus, per split of the
+ * point range, that again and 8 bytes per padded plan: about 3,000 plans at
+ * 512 dwells with one split), else EINVAL.  The split count is the context's,
+ * lowered to what fits.  Every call on a device shares that device's array:
+ * calls that overlap on one device (several streams or threads) race.
+ * Errors: EINVAL, ESTATE, EHIP. */
+int gmco_evaluate_noalloc(gmco_ctx* ctx, const double* x_dev, double* F_dev, double* g_dev);
+
 /* Run batched L-BFGS until every plan has stopped (converged, max_iter,
  * line-search failure) or info reports the state.  Continues from the
  * current state: plans stopped by max_iter resume if run->max_iter is larger.

@@ -29,7 +29,7 @@ EXPORTS = (
     "gmco_optimize", "gmco_get_dwell_times", "gmco_get_weights_x", "gmco_get_metrics",
     "gmco_get_dose_rate", "gmco_get_start_time", "gmco_case_features", "gmco_optimize_many",
     "gmco_autotune", "gmco_set_split", "gmco_select_plan", "gmco_state_bytes",
-    "gmco_get_state", "gmco_set_state", "gmco_last_error",
+    "gmco_get_state", "gmco_set_state", "gmco_evaluate_noalloc", "gmco_last_error",
     "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
     "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
     "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
@@ -134,6 +134,7 @@ def load_library(path: Optional[str] = None):
     lib.gmco_set_split.argtypes = [vp, C.c_int]
     lib.gmco_select_plan.argtypes = [vp, C.POINTER(gmco_select_opts), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+    lib.gmco_evaluate_noalloc.argtypes = [vp, vp, vp, vp]
     lib.gmco_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     lib.gmco_get_state.argtypes = [vp, vp, C.c_size_t]
     lib.gmco_set_state.argtypes = [vp, vp, C.c_size_t]
@@ -318,6 +319,12 @@ class Planner:
         g = np.empty((self.P, self.K))
         self._check(self.lib.gmco_evaluate(self._ctx, _dptr(x), _dptr(F), _dptr(g)), "evaluate")
         return F, g
+
+    def evaluate_noalloc(self, x_ptr: int, F_ptr: int, g_ptr: int):
+        """gmco_evaluate_noalloc on device arrays (FP64: x P x K, F P, g P x K),
+        enqueued on the context stream."""
+        self._check(self.lib.gmco_evaluate_noalloc(self._ctx, C.c_void_p(x_ptr), C.c_void_p(F_ptr),
+                                                   C.c_void_p(g_ptr)), "evaluate_noalloc")
 
     def optimize(self, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
                  max_ls: int = 30, check_every: int = 16, time_kernels: int = 0,

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -898,6 +899,69 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     if (rc && !status) status = rc;
   }
   return status;
+}
+
+}  // extern "C"
+
+// ---- evaluation with library-held scratch (no allocation) ----
+// The evaluation's split partials and its FP32 copy of x live in this array,
+// one per device, held until the process ends.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current).
+hipError_t static_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int gmco_evaluate_noalloc(gmco_ctx* c, const double* x_dev, double* F_dev, double* g_dev) {
+  if (!c || !x_dev || !F_dev || !g_dev) return GMCO_EINVAL;
+  if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
+  const Dims& d = c->dim;
+  const bool lp = is_low_precision(c->dtype);
+  const int units = lp ? (d.ntiles + d.lpt - 1) / d.lpt : d.ntiles;
+  const size_t PK = (size_t)d.Pp * d.Kp;
+  const size_t xe_bytes = align256(PK * 4);
+  const size_t per_split = align256(PK * 4) + align256((size_t)d.Pp * 8);
+  if (xe_bytes + per_split > kStaticScratchBytes)
+    return fail(c, GMCO_EINVAL, "batch too large for the 32 MiB evaluation scratch (plans x padded dwells)");
+  // the context's split, lowered until the partials fit the scratch
+  int S = lp ? d.S_lp : d.S;
+  S = std::min(S, (int)((kStaticScratchBytes - xe_bytes) / per_split));
+  GMCO_HIP(c, hipSetDevice(c->device));
+  void* base = nullptr;
+  GMCO_HIP(c, static_scratch(c->device, &base));
+  char* b = static_cast<char*>(base);
+  float* xe = reinterpret_cast<float*>(b);
+  float* Gpart = reinterpret_cast<float*>(b + xe_bytes);
+  double* Fpart = reinterpret_cast<double*>(b + xe_bytes + align256((size_t)S * PK * 4));
+  GMCO_HIP(c, launch_x_to_device(x_dev, c->P, d.Pp, d.K, d.Kp, xe, c->stream));
+  EvalArgs a = eval_args(c, xe, false, c->dtype);
+  a.S = S;
+  a.grid = S * units;
+  a.Gpart = Gpart;
+  a.Fpart = Fpart;
+  GMCO_HIP(c, launch_eval(a, c->dtype, c->stream));
+  GMCO_HIP(c, launch_finish_eval(Gpart, Fpart, xe, S, c->P, d.Pp, d.K, d.Kp, F_dev, g_dev, c->stream));
+  return GMCO_OK;
 }
 
 int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best_us) {
