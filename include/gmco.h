@@ -133,7 +133,10 @@ typedef struct {
                          F32 and F32_ACC64 are always available; BF16 and FP8 need a
                          context created with that dtype.  Successive runs with
                          rising precision form a precision ladder on one state. */
-  int reserved;
+  int per_case_launches; /* gmco_optimize_many only: 0 groups the cases (per round, one
+                         evaluation launch per padded dwell count and dtype, one
+                         reduction launch, one update launch per update shape);
+                         1 issues every case's kernels as launches of their own */
 } gmco_run;
 
 typedef struct {
@@ -268,11 +271,17 @@ int gmco_select_plan(gmco_ctx* ctx, const gmco_select_opts* opts, int* best, int
 
 /* Batched uneven cases: run the same options on n contexts (one case and
  * weight batch each, one device) in lockstep rounds on the first context's
- * stream.  rounds_per_graph > 0 captures that many rounds (rounded up to even)
- * of every case into one HIP graph and replays it until every plan of every
- * case has stopped; 0 issues plain launches.  infos has n entries (NULL
- * allowed); device_ms is the whole batch's time.  Plans that stop early keep
- * compacted out of every later round on the device.  Errors as gmco_optimize. */
+ * stream.  Each round evaluates every case's running plans, in one grouped
+ * launch per padded dwell count (a table maps each workgroup to its case),
+ * then reduces and updates them in grouped launches (run->per_case_launches
+ * = 1: separate launches per case, with identical results).
+ * rounds_per_graph > 0 captures that many rounds (rounded up to even) into
+ * one HIP graph and replays it until every plan of every case has stopped;
+ * 0 issues plain launches.  infos has n entries (NULL allowed); device_ms is
+ * the whole batch's time.  Plans that stop early keep compacted out of every
+ * later round on the device.  The grouped form allocates its argument tables
+ * (a few hundred bytes per case) for the call.  Errors as gmco_optimize,
+ * ENOMEM. */
 int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_run_info* infos,
                        int rounds_per_graph);
 

@@ -65,7 +65,7 @@ class gmco_run(C.Structure):
     _fields_ = [("max_iter", C.c_int), ("eps", C.c_double), ("c1", C.c_double),
                 ("beta", C.c_double), ("max_ls", C.c_int), ("check_every", C.c_int),
                 ("time_kernels", C.c_int), ("resume_stopped", C.c_int), ("dtype", C.c_int),
-                ("reserved", C.c_int)]
+                ("per_case_launches", C.c_int)]
 
 
 class gmco_select_opts(C.Structure):
@@ -419,13 +419,15 @@ class Planner:
 
 def optimize_many(planners, max_iter: int, eps: float = 0.0, c1: float = 1e-4, beta: float = 0.5,
                   max_ls: int = 30, check_every: int = 16, rounds_per_graph: int = 16,
-                  resume_stopped: bool = False, dtype: Optional[str] = None):
+                  resume_stopped: bool = False, dtype: Optional[str] = None,
+                  per_case_launches: bool = False):
     """Lockstep batched L-BFGS over several cases (gmco_optimize_many)."""
     lib = load_library()
     n = len(planners)
     arr = (C.c_void_p * n)(*[p._ctx.value for p in planners])
     r = gmco_run(int(max_iter), float(eps), float(c1), float(beta), int(max_ls), int(check_every),
-                 0, int(bool(resume_stopped)), -1 if dtype is None else DTYPES[dtype], 0)
+                 0, int(bool(resume_stopped)), -1 if dtype is None else DTYPES[dtype],
+                 int(bool(per_case_launches)))
     infos = (gmco_run_info * n)()
     rc = lib.gmco_optimize_many(arr, n, C.byref(r), infos, int(rounds_per_graph))
     if rc != 0:

@@ -824,7 +824,96 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     as[i] = eval_args(c, c->at<float>(L.xt), true, dtypes[i]);
   }
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
+  // Grouped launches: the cases' evaluations by (padded dwells, dtype), one
+  // reduction for all, the updates by (update width, history capacity); the
+  // argument tables live in one device buffer for the call.
+  const bool grouped = r->per_case_launches == 0 && n > 1;
+  struct Bucket {
+    int key0, key1;           // (Kp, dtype) or (E, MH)
+    std::vector<int> cases;
+    int off = 0, soff = 0, grid = 0, pp_max = 0;
+  };
+  std::vector<Bucket> eb, ub;
+  void* dtab = nullptr;
+  struct TabGuard {
+    void*& p;
+    ~TabGuard() {
+      if (p) hipFree(p);
+    }
+  } tab_guard{dtab};
+  EvalArgs* d_eargs = nullptr;
+  int* d_start = nullptr;
+  UpdateArgs* d_uargs = nullptr;
+  ReduceArgs* d_rargs = nullptr;
+  long long red_threads = 1;
+  if (grouped) {
+    auto bucket_of = [](std::vector<Bucket>& v, int k0, int k1) -> Bucket& {
+      for (Bucket& b : v)
+        if (b.key0 == k0 && b.key1 == k1) return b;
+      v.push_back(Bucket{k0, k1, {}});
+      return v.back();
+    };
+    auto mh = [](int m) { return m <= 4 ? 4 : (m <= 10 ? 10 : (m <= 16 ? 16 : GMCO_MAX_HISTORY)); };
+    for (int i = 0; i < n; ++i) {
+      bucket_of(eb, ctxs[i]->dim.Kp, dtypes[i]).cases.push_back(i);
+      bucket_of(ub, update_width(ctxs[i]->dim.Kp), mh(ctxs[i]->m)).cases.push_back(i);
+    }
+    std::vector<EvalArgs> he;
+    std::vector<int> hs;
+    for (Bucket& b : eb) {
+      b.off = (int)he.size();
+      b.soff = (int)hs.size();
+      int g = 0;
+      for (int i : b.cases) {
+        he.push_back(as[i]);
+        hs.push_back(g);
+        g += (as[i].grid + 7) / 8 * 8;  // each case starts on a multiple of 8 (XCD placement)
+      }
+      hs.push_back(g);
+      b.grid = g;
+    }
+    std::vector<UpdateArgs> hu;
+    for (Bucket& b : ub) {
+      b.off = (int)hu.size();
+      for (int i : b.cases) {
+        hu.push_back(us[i]);
+        b.pp_max = std::max(b.pp_max, ctxs[i]->dim.Pp);
+      }
+    }
+    std::vector<ReduceArgs> hr(n);
+    for (int i = 0; i < n; ++i) {
+      gmco_ctx* c = ctxs[i];
+      hr[i] = ReduceArgs{as[i].Gpart, as[i].rt, c->at<float>(c->lay.Gsum), c->dim.Kp, 0};
+      red_threads = std::max(red_threads, (long long)c->dim.Pp * (c->dim.Kp / 4));
+    }
+    const size_t be = align256(he.size() * sizeof(EvalArgs)), bs = align256(hs.size() * sizeof(int));
+    const size_t bu = align256(hu.size() * sizeof(UpdateArgs)), br = align256(hr.size() * sizeof(ReduceArgs));
+    if (hipMalloc(&dtab, be + bs + bu + br) != hipSuccess) {
+      dtab = nullptr;
+      return fail(c0, GMCO_ENOMEM, "argument tables of the grouped launches");
+    }
+    char* base = static_cast<char*>(dtab);
+    d_eargs = reinterpret_cast<EvalArgs*>(base);
+    d_start = reinterpret_cast<int*>(base + be);
+    d_uargs = reinterpret_cast<UpdateArgs*>(base + be + bs);
+    d_rargs = reinterpret_cast<ReduceArgs*>(base + be + bs + bu);
+    GMCO_HIP(c0, hipMemcpyAsync(d_eargs, he.data(), he.size() * sizeof(EvalArgs), hipMemcpyHostToDevice, st));
+    GMCO_HIP(c0, hipMemcpyAsync(d_start, hs.data(), hs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    GMCO_HIP(c0, hipMemcpyAsync(d_uargs, hu.data(), hu.size() * sizeof(UpdateArgs), hipMemcpyHostToDevice, st));
+    GMCO_HIP(c0, hipMemcpyAsync(d_rargs, hr.data(), hr.size() * sizeof(ReduceArgs), hipMemcpyHostToDevice, st));
+    GMCO_HIP(c0, hipStreamSynchronize(st));  // the host tables above are freed on return
+  }
   auto issue_round = [&](long long rd) -> int {
+    if (grouped) {
+      for (const Bucket& b : eb)
+        GMCO_HIP(c0, launch_eval_grouped(d_eargs + b.off, d_start + b.soff, (int)b.cases.size(), b.grid, b.key0,
+                                         b.key1, st));
+      GMCO_HIP(c0, launch_reduce_g_grouped(d_rargs, n, red_threads, st));
+      for (const Bucket& b : ub)
+        GMCO_HIP(c0, launch_update_grouped(d_uargs + b.off, (int)b.cases.size(), b.key0, b.pp_max, b.key1,
+                                           (int)rd, st));
+      return GMCO_OK;
+    }
     for (int i = 0; i < n; ++i) {
       us[i].round = (int)rd;
       GMCO_HIP(ctxs[i], launch_eval(as[i], dtypes[i], st));

@@ -128,6 +128,18 @@ struct UpdateArgs {
   int round;
 };
 
+// Arguments of one case's split-partial reduction (grouped launches).
+struct ReduceArgs {
+  const float* Gpart;
+  const RoundTable* rt;
+  float* Gsum;
+  int Kp, pad;
+};
+
+// Update kernel lane layout: groups of four dwells per lane, E values per
+// lane (4 up to 256 padded dwells, 8 up to 512).
+__host__ __device__ constexpr int update_width(int Kp) { return Kp <= 256 ? 4 : (Kp <= 512 ? 8 : 0); }
+
 // ---- launchers (each defined next to its kernels) ----
 hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
                             const int* perm, int M, int K, int Mp, int Kp, double* D64,
@@ -143,6 +155,16 @@ hipError_t launch_init_plans(int P, int Pp, int K, int Kp, const double* t0, con
                              float* xt, float* x, float* wn, double* W64, PlanState* ps,
                              hipStream_t st);
 hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st);
+// Several cases of one padded dwell count Kp in one launch: case c's
+// workgroups are start[c] .. start[c + 1] - 1 of grid (start[c] a multiple
+// of 8), its arguments args[c] (device arrays, n entries / n + 1 starts).
+hipError_t launch_eval_grouped(const EvalArgs* args, const int* start, int n, int grid, int Kp, int dtype,
+                               hipStream_t st);
+// Update / reduction of n cases in one launch (cases of one update width E
+// for the update); grids sized for the largest case.
+hipError_t launch_update_grouped(const UpdateArgs* args, int n, int E, int Pp_max, int m, int round,
+                                 hipStream_t st);
+hipError_t launch_reduce_g_grouped(const ReduceArgs* args, int n, long long max_threads, hipStream_t st);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t st);
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
                               int P, int Pp, int K, int Kp, double* F, double* g,

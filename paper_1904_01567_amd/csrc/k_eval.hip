@@ -54,7 +54,7 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
 }
 
 // Resolves the evaluation's shape (split count S, tile count, row stride of
-// the partial buffers), this workgroup's (split, first compact column j0) and
+// the partial buffers), workgroup bid's (split, first compact column j0) and
 // the plan behind each of its TPW * kPT columns (-1: empty), and stages the
 // columns' structure weights.  In a compacted round every workgroup ranks
 // the running plans itself (a block-wide scan of the flags), so no separate
@@ -63,7 +63,7 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile)
 // `stride` (the second tile of the last workgroup when ntiles is odd) are
 // empty and have no partials.
 template <int NT, int TPW = 1>
-__device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, float* sW, int& s,
+__device__ inline bool tile_setup(const EvalArgs& a, int bid, int* sPlan, int* sScan, float* sW, int& s,
                                   int& S, int& stride, int& j0) {
   constexpr int NCOL = TPW * kPT;
   const int tid = threadIdx.x;
@@ -73,8 +73,8 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     S = a.S;
     stride = a.Pp;
     const int units = (a.ntiles + TPW - 1) / TPW;
-    if ((int)blockIdx.x >= S * units) return false;
-    split_tile(blockIdx.x, S, units, s, unit);
+    if (bid >= S * units) return false;
+    split_tile(bid, S, units, s, unit);
     j0 = unit * NCOL;
     for (int i = tid; i < NCOL; i += NT) sPlan[i] = j0 + i < a.Pp ? j0 + i : -1;
   } else {
@@ -102,7 +102,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
     const int ntiles = (nact + kPT - 1) / kPT;
     S = (a.s_tuned > 0 && ntiles == a.ntiles) ? a.s_tuned : a.split_tab[ntiles];
     stride = ntiles * kPT;
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bid == 0 && tid == 0) {
       RoundTable r;
       r.nact = nact;
       r.ntiles = ntiles;
@@ -113,8 +113,8 @@ __device__ inline bool tile_setup(const EvalArgs& a, int* sPlan, int* sScan, flo
       if (a.work2 != nullptr) *a.work2 += (unsigned long long)nact;
     }
     const int units = (ntiles + TPW - 1) / TPW;
-    if ((int)blockIdx.x >= S * units) return false;
-    split_tile(blockIdx.x, S, units, s, unit);
+    if (bid >= S * units) return false;
+    split_tile(bid, S, units, s, unit);
     j0 = unit * NCOL;
     int r = base + v - cnt;
     for (int p = b; p < e; ++p) {
@@ -147,7 +147,7 @@ __device__ inline int swz_row(int row) { return (row >> 1) & 3; }
 enum { MODE_F32 = 0, MODE_CHUNK64 = 2 };
 
 template <int KP, int MODE>
-__global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
+__device__ inline void eval_f32(const EvalArgs& a, int bid) {
   // LDS row stride (floats): the dose product reads rows n = 0..15 as float4
   // at one column, the back-projection 16 consecutive columns of rows
   // 4q + r; Kp + 4 is conflict-free for both.
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
   const int n = lane & 15;
 
   int s, S, stride, j0;
-  if (!tile_setup<256>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<256>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
 // 0..15 conflict-free.
 // ---------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
+__device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   constexpr int NT = 512;
   constexpr int KS = KP + 16;
   constexpr int NKH = KP / 32;      // 16-dwell slices per dwell half
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
   const int half = wave >> 2; // dwell half: slices half * NKH .. half * NKH + NKH - 1
 
   int s, S, stride, j0;
-  if (!tile_setup<NT>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<NT>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -580,7 +580,7 @@ struct LpOp<true> {
 };
 
 template <int KP, bool FP8>
-__device__ inline void eval_lp(const EvalArgs& a) {
+__device__ inline void eval_lp(const EvalArgs& a, int bid) {
   typedef typename LpOp<FP8>::type op_t;
   constexpr int BMP = 32;              // points per block
   // D tile row stride (BF16 elements or FP8 bytes) and transposed tile row
@@ -626,7 +626,7 @@ __device__ inline void eval_lp(const EvalArgs& a) {
     for (int j = 0; j <= kGmax; ++j) sP[j] = a.gt.prm[j];
   }
   int s, S, stride, j0;  // (tile_setup ends with a barrier)
-  if (!tile_setup<NT, TPW>(a, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<NT, TPW>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
 
   // B operands of the dose product, t = x^2 at dwells 32 k + 8 q + e, for
   // the plans of columns 16 (NH wave + h) + n (an empty column evaluates t = 0
@@ -880,14 +880,62 @@ __device__ inline void eval_lp(const EvalArgs& a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Kernels.  Each evaluation exists as a single-case kernel (workgroup id =
+// blockIdx.x) and as a grouped kernel over several cases of one padded dwell
+// count: grouped workgroup g belongs to the case c with start[c] <= g <
+// start[c + 1] (each case's range begins at a multiple of 8, so the XCD
+// placement of its tiles is as in a launch of its own) and runs as that
+// case's workgroup g - start[c], with the case's arguments from args[c].
+// ---------------------------------------------------------------------------
+__device__ inline int group_case(const int* __restrict__ start, int n, int g) {
+  int c = 0;
+  while (c + 1 < n && start[c + 1] <= g) ++c;
+  return c;
+}
+
+template <int KP, int MODE>
+__global__ __launch_bounds__(256, 1) void k_eval_f32(EvalArgs a) {
+  eval_f32<KP, MODE>(a, blockIdx.x);
+}
+template <int KP, int MODE>
+__global__ __launch_bounds__(256, 1) void k_eval_f32_grouped(const EvalArgs* __restrict__ args,
+                                                             const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_f32<KP, MODE>(args[c], blockIdx.x - start[c]);
+}
+
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
+  eval_acc64<KP>(a, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_acc64_grouped(const EvalArgs* __restrict__ args,
+                                                               const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_acc64<KP>(args[c], blockIdx.x - start[c]);
+}
+
 template <int KP>
 __global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_bf16(EvalArgs a) {
-  eval_lp<KP, false>(a);
+  eval_lp<KP, false>(a, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_bf16_grouped(const EvalArgs* __restrict__ args,
+                                                                         const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_lp<KP, false>(args[c], blockIdx.x - start[c]);
 }
 
 template <int KP>
 __global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_fp8(EvalArgs a) {
-  eval_lp<KP, true>(a);
+  eval_lp<KP, true>(a, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_fp8_grouped(const EvalArgs* __restrict__ args,
+                                                                        const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_lp<KP, true>(args[c], blockIdx.x - start[c]);
 }
 
 template <int KP>
@@ -909,6 +957,25 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int KP>
+hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int grid, int dtype,
+                             hipStream_t st) {
+  if (grid < 1 || n < 1) return hipErrorInvalidValue;
+  if (dtype == GMCO_DTYPE_F32_ACC64)
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP>), dim3(grid), dim3(512), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32_CHUNK64)
+    hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_CHUNK64>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32)
+    hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_F32>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_BF16)
+    hipLaunchKernelGGL((k_eval_bf16_grouped<KP>), dim3(grid), dim3(lp_threads(KP)), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_FP8)
+    hipLaunchKernelGGL((k_eval_fp8_grouped<KP>), dim3(grid), dim3(lp_threads(KP)), 0, st, args, start, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st) {
@@ -916,6 +983,34 @@ hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st) {
 #define GMCO_KP_CASE(v) \
   case v:               \
     return launch_kp<v>(a, dtype, st);
+    GMCO_KP_CASE(32)
+    GMCO_KP_CASE(64)
+    GMCO_KP_CASE(96)
+    GMCO_KP_CASE(128)
+    GMCO_KP_CASE(160)
+    GMCO_KP_CASE(192)
+    GMCO_KP_CASE(224)
+    GMCO_KP_CASE(256)
+    GMCO_KP_CASE(288)
+    GMCO_KP_CASE(320)
+    GMCO_KP_CASE(352)
+    GMCO_KP_CASE(384)
+    GMCO_KP_CASE(416)
+    GMCO_KP_CASE(448)
+    GMCO_KP_CASE(480)
+    GMCO_KP_CASE(512)
+#undef GMCO_KP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_eval_grouped(const EvalArgs* args, const int* start, int n, int grid, int Kp, int dtype,
+                               hipStream_t st) {
+  switch (Kp) {
+#define GMCO_KP_CASE(v) \
+  case v:               \
+    return launch_kp_grouped<v>(args, start, n, grid, dtype, st);
     GMCO_KP_CASE(32)
     GMCO_KP_CASE(64)
     GMCO_KP_CASE(96)

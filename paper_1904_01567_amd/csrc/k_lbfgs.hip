@@ -133,10 +133,10 @@ __device__ inline void store_vec(float* __restrict__ dst, int lane, int Kp, cons
 // registers in age order (0 = newest) so every loop index is a compile-time
 // constant; all their loads are issued together before the recursion.
 template <int E, int MH>
-__global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
+__device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
   const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.active_count[(a.round + 1) & 1] = 0;
+  const int p = bx * 4 + (threadIdx.x >> 6);
+  if (bx == 0 && threadIdx.x == 0) a.active_count[(round + 1) & 1] = 0;
   if (p >= a.Pp) return;
   const int Kp = a.Kp;
   const int m = a.m;
@@ -327,8 +327,20 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
   if (lane == 0) {
     a.ps[p] = st;
     a.flag[p] = state_active(st.status) ? 1 : 0;
-    if (state_active(st.status)) atomicAdd(&a.active_count[a.round & 1], 1);
+    if (state_active(st.status)) atomicAdd(&a.active_count[round & 1], 1);
   }
+}
+
+template <int E, int MH>
+__global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
+  update_plans<E, MH>(a, blockIdx.x, a.round);
+}
+
+// Grouped form: case blockIdx.y of n, its arguments from args (their round
+// field is not used; all cases are in the same round).
+template <int E, int MH>
+__global__ __launch_bounds__(256) void k_update_grouped(const UpdateArgs* __restrict__ args, int round) {
+  update_plans<E, MH>(args[blockIdx.y], blockIdx.x, round);
 }
 
 template <int E>
@@ -341,14 +353,25 @@ hipError_t launch_update_e(const UpdateArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int E>
+hipError_t launch_update_grouped_e(const UpdateArgs* args, int n, int Pp_max, int m, int round,
+                                   hipStream_t st) {
+  const dim3 grid((Pp_max + 3) / 4, n), block(256);
+  if (m <= 4) hipLaunchKernelGGL((k_update_grouped<E, 4>), grid, block, 0, st, args, round);
+  else if (m <= 10) hipLaunchKernelGGL((k_update_grouped<E, 10>), grid, block, 0, st, args, round);
+  else if (m <= 16) hipLaunchKernelGGL((k_update_grouped<E, 16>), grid, block, 0, st, args, round);
+  else hipLaunchKernelGGL((k_update_grouped<E, GMCO_MAX_HISTORY>), grid, block, 0, st, args, round);
+  return hipGetLastError();
+}
+
 // Sum of the split-M gradient partials of every compact column, in split
 // order: one thread per (column, 4 dwells), so the sum has the whole chip's
 // parallelism however many splits a round uses.
-__global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpart, const RoundTable* rt,
-                                                  int Kp, float* __restrict__ Gsum) {
+__device__ inline void reduce_g(const float* __restrict__ Gpart, const RoundTable* rt, int Kp,
+                                float* __restrict__ Gsum, int bx) {
   const RoundTable r = *rt;
   const int nq = Kp / 4;
-  const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long idx = (long long)bx * 256 + threadIdx.x;
   const int j = (int)(idx / nq);
   const int c = (int)(idx - (long long)j * nq);
   if (j >= r.nact) return;
@@ -376,6 +399,17 @@ __global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpar
     acc.w += v.w;
   }
   reinterpret_cast<float4*>(Gsum + (size_t)j * Kp)[c] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpart, const RoundTable* rt,
+                                                  int Kp, float* __restrict__ Gsum) {
+  reduce_g(Gpart, rt, Kp, Gsum, blockIdx.x);
+}
+
+// Grouped form: case blockIdx.y.
+__global__ __launch_bounds__(256) void k_reduce_g_grouped(const ReduceArgs* __restrict__ args) {
+  const ReduceArgs& a = args[blockIdx.y];
+  reduce_g(a.Gpart, a.rt, a.Kp, a.Gsum, blockIdx.x);
 }
 
 // Partial reduction for a stand-alone evaluation: F = sum_s Fpart, g = 4 x G.
@@ -425,6 +459,19 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t st) {
   if (a.Kp <= 256) return launch_update_e<4>(a, st);
   if (a.Kp <= 512) return launch_update_e<8>(a, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_update_grouped(const UpdateArgs* args, int n, int E, int Pp_max, int m, int round,
+                                 hipStream_t st) {
+  if (E == 4) return launch_update_grouped_e<4>(args, n, Pp_max, m, round, st);
+  if (E == 8) return launch_update_grouped_e<8>(args, n, Pp_max, m, round, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_g_grouped(const ReduceArgs* args, int n, long long max_threads, hipStream_t st) {
+  const dim3 grid((unsigned)((max_threads + 255) / 256), n);
+  hipLaunchKernelGGL(k_reduce_g_grouped, grid, dim3(256), 0, st, args);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,

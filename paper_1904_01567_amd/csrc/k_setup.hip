@@ -206,15 +206,20 @@ __global__ void k_learned_start(const float* __restrict__ Y, int K, int Kp, cons
   }
 }
 
-// Per plan: keep the learned start only where its objective is finite and
-// below the uniform start's (plain L-BFGS from the uniform start is the
-// fallback).  The chosen point becomes the plan's start (status INIT).
+// Per plan: keep the learned start only where it is finite and its
+// objective is below the uniform start's (plain L-BFGS from the uniform
+// start is the fallback).  The start itself is checked, not only F: the
+// penalty of eq. 1 as evaluated (min / max with the band edges) is 0 at a
+// NaN dose.  The chosen point becomes the plan's start (status INIT).
 __global__ void k_pick_start(const double* __restrict__ Fw, const double* __restrict__ Fu,
                              const float* __restrict__ xe, int Kp, float* __restrict__ x,
                              float* __restrict__ xt, int* __restrict__ n_warm, int* __restrict__ use_warm) {
   const int p = blockIdx.x;
+  int bad = 0;
+  for (int l = threadIdx.x; l < Kp; l += blockDim.x) bad |= !isfinite(xe[(size_t)p * Kp + l]);
+  bad = __syncthreads_or(bad);
   const double fw = Fw[p];
-  const bool warm = isfinite(fw) && fw < Fu[p];
+  const bool warm = !bad && isfinite(fw) && fw < Fu[p];
   if (threadIdx.x == 0) {
     use_warm[p] = warm ? 1 : 0;
     if (warm) atomicAdd(n_warm, 1);
