@@ -94,8 +94,9 @@ def golden_path(all_plans: bool = True):
 
 
 def load_golden():
-    """The oracle optima of every plan of the batch when stored, else those of
-    the 64-plan sample, as (plan indices, F*, target V100*)."""
+    """The oracle optima of every plan of the batch when stored (the merged
+    file, else the shares written so far), else those of the 64-plan sample,
+    as (plan indices, F*, target V100*)."""
     import numpy as np
     p = golden_path(True)
     if os.path.exists(p):
@@ -103,6 +104,18 @@ def load_golden():
             g = json.load(fh)
         return (np.arange(len(g["F"])), np.array(g["F"]),
                 np.array([v[0] for v in g["V100_pct"]]))
+    parts = os.path.join(ROOT, "tests", "golden", "c2_optima_parts")
+    if os.path.isdir(parts) and os.listdir(parts):
+        idx, F, V = [], [], []
+        for name in sorted(os.listdir(parts)):
+            if not name.endswith(".json"):
+                continue
+            with open(os.path.join(parts, name)) as fh:
+                q = json.load(fh)
+            idx += list(range(q["lo"], q["hi"]))
+            F += q["F"]
+            V += [v[0] for v in q["V100_pct"]]
+        return np.array(idx), np.array(F), np.array(V)
     p = golden_path(False)
     if not os.path.exists(p):
         return None
@@ -438,29 +451,29 @@ def precision_report(args) -> int:
 
 
 def batched(args) -> int:
-    """Uneven-case batch: one context per case, lockstep rounds replayed from
-    a captured graph; split counts autotuned once per (padded dwells, point
-    bucket) shape and reused."""
+    """Uneven-case batch (64 cases, dwells 120-400, points 8k-30k, 1,000 plans
+    each): one context per case, grouped lockstep rounds replayed from a
+    captured graph, the headline's stages and stop rule; split counts
+    autotuned per case and kernel family.  The cases that have oracle optima
+    (tests/golden/c4_reference_optima.json) are checked against them."""
+    import numpy as np
     import torch
 
     import cases
     from paper_1904_01567_amd import Planner, class_solution, optimize_many
-    iters = args.iters or ITERS.get(args.dtype, 2000)
+    stages = args.stages
+    run_eps = DEFAULT_EPS if args.eps is None else args.eps
     side = torch.cuda.Stream()
-    planners, Ws, shapes = [], [], []
-    tune_cache = {}
+    planners, Ws, shapes, splits = [], [], [], []
     t0 = time.perf_counter()
     with torch.cuda.stream(side):
         for i in range(args.batched):
             c = cases.case_batch(i)
             W = cases.hidden_weights(args.plans, seed=2000 + i)
-            pl = Planner(dtype=args.dtype, max_plans=args.plans)
+            pl = Planner(dtype=stages[0][0], max_plans=args.plans, history=args.history)
             pl.load(c, class_solution.VOLUME)
             pl.set_weights(W)
-            key = ((c.K + 31) // 32 * 32, (c.M + 4095) // 4096)
-            if key not in tune_cache:
-                tune_cache[key] = pl.autotune(reps=3)[0]
-            pl.set_split(tune_cache[key])
+            splits.append([pl.autotune(dtype=d, reps=3)[0] for d in sorted({d for d, _ in stages})])
             planners.append(pl)
             Ws.append(W)
             shapes.append((c.K, c.M))
@@ -472,37 +485,69 @@ def batched(args) -> int:
         with torch.cuda.stream(side):
             for pl, W in zip(planners, Ws):
                 pl.set_weights(W)
-            infos = optimize_many(planners, max_iter=iters, rounds_per_graph=args.rounds_per_graph)
+            per_stage = []
+            for k, (dt, cap) in enumerate(stages):
+                per_stage.append(optimize_many(planners, max_iter=cap, eps=run_eps, dtype=dt,
+                                               resume_stopped=k > 0, rounds_per_graph=args.rounds_per_graph))
             for pl in planners:
                 pl.dwell_times()
-                pl.metrics()
         torch.cuda.synchronize()
-        return infos
+        return per_stage
 
     for _ in range(args.warmup):
         step()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        infos = step()
-        print(f"# step {k + 1}/{args.steps}: {infos[0]['rounds']} rounds, "
-              f"{infos[0]['device_ms']:.0f} ms device", file=sys.stderr, flush=True)
+        per_stage = step()
+        print(f"# step {k + 1}/{args.steps}: rounds per stage {[i[0]['rounds'] for i in per_stage]}, "
+              f"{sum(i[0]['device_ms'] for i in per_stage):.0f} ms device", file=sys.stderr, flush=True)
     elapsed = (time.perf_counter() - t0) / args.steps
     n_plans = args.batched * args.plans
-    flops = [4.0 * M * K * args.plans for K, M in shapes]
-    work = [i["eval_work"] for i in infos]
+    # tolerance against the oracle optima of the sampled plans of the first cases
+    tol = None
+    gp = os.path.join(ROOT, "tests", "golden", "c4_reference_optima.json")
+    if os.path.exists(gp):
+        with open(gp) as fh:
+            gold = json.load(fh)
+        rel_max, dv_max, checked, within = -1.0, 0.0, 0, 0
+        for row in gold["cases"]:
+            if row["index"] >= args.batched or args.plans != gold["plans_per_case"]:
+                continue
+            m = planners[row["index"]].metrics()
+            idx = np.array([q["index"] for q in row["plans"]])
+            rel = (m["F64"][idx] - np.array([q["F"] for q in row["plans"]])) / np.array([q["F"] for q in row["plans"]])
+            dv = np.abs(m["V100_pct"][idx, 0] - np.array([q["V100_pct"] for q in row["plans"]]))
+            rel_max, dv_max = max(rel_max, float(rel.max())), max(dv_max, float(dv.max()))
+            checked += idx.size
+            within += int(np.sum((rel <= TOL_F) & (dv <= TOL_V100)))
+        tol = dict(checked_plans=checked, within_tol=within, max_rel_F_excess=rel_max,
+                   max_abs_dV100_pp=dv_max)
+    flops = np.array([4.0 * M * K * args.plans for K, M in shapes])
+    last = per_stage[-1]
+    last_ms = last[0]["device_ms"]
+    work = np.array([i["eval_work"] for i in last])
+    achieved = float(np.sum(flops * work)) / (last_ms / 1e3) / 1e12
+    peak = eval_peak_tflops(stages[-1][0])
     out = {
-        "metric": "plans/sec over a batch of uneven cases (lockstep rounds, graph replay)",
+        "metric": "plans/sec over a batch of uneven cases (grouped lockstep rounds, graph replay)",
         "value": n_plans / elapsed, "unit": "plans/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed, "higher_is_better": True,
-        "dtype": DTYPE_NAMES[args.dtype], "data": "synthetic",
+        "dtype": " -> ".join(DTYPE_NAMES[d] for d, _ in stages), "data": "synthetic",
         "config": {"workload": f"{args.batched} cases, dwells {min(k for k, _ in shapes)}-"
                                f"{max(k for k, _ in shapes)}, points {min(m for _, m in shapes)}-"
-                               f"{max(m for _, m in shapes)}, {args.plans} plans each, "
-                               f"{iters} iterations, graph of {args.rounds_per_graph} rounds",
-                   "cases": args.batched, "plans_per_case": args.plans, "iterations": iters},
-        "rounds": infos[0]["rounds"], "device_ms": infos[0]["device_ms"],
-        "evaluation_tflops_avg": sum(f * w for f, w in zip(flops, work)) / (infos[0]["device_ms"] / 1e3) / 1e12,
-        "autotuned_splits": {f"{k[0]}x{k[1] * 4096}": v for k, v in tune_cache.items()},
+                               f"{max(m for _, m in shapes)}, {args.plans} plans each, stages "
+                               f"{','.join(f'{d}:{n}' for d, n in stages)}, stop at relative objective "
+                               f"variation {run_eps:g}, graph of {args.rounds_per_graph} rounds",
+                   "cases": args.batched, "plans_per_case": args.plans,
+                   "stages": [f"{d}:{n}" for d, n in stages], "eps": run_eps},
+        "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
+        "rounds_per_stage": [i[0]["rounds"] for i in per_stage],
+        "device_ms_per_stage": [i[0]["device_ms"] for i in per_stage],
+        "last_stage_rate": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                            "frac": achieved / peak,
+                            "note": "evaluation FLOPs of the last stage / its whole device time "
+                                    "(reductions and updates included)"},
+        "autotuned_splits": splits,
         "setup_s": t_setup,
     }
     print(json.dumps(out), flush=True)
@@ -522,6 +567,7 @@ def main(argv=None) -> int:
                          "cumulative); the context is created with the first dtype")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
+    ap.add_argument("--history", type=int, default=10, help="L-BFGS pairs m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-plans", type=int, default=16,
                     help="plans of the oracle's host timing, spread over the batch")
@@ -594,6 +640,11 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n}), flush=True)
         return 0
+    if not one_stage and not args.ladder:
+        args.ladder = DEFAULT_LADDER
+    args.stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
+    if args.ladder:
+        args.stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]
     if args.batched:
         return batched(args)
     if args.precision_report:
@@ -606,17 +657,13 @@ def main(argv=None) -> int:
         return surface_volume(args)
     if args.warm_start_compare:
         return warm_start_compare(args)
-    if not one_stage and not args.ladder:
-        args.ladder = DEFAULT_LADDER
-    stages = [(args.dtype, args.iters or ITERS.get(args.dtype, 2000))]
-    if args.ladder:
-        stages = [(st.split(":")[0], int(st.split(":")[1])) for st in args.ladder.split(",")]
+    stages = args.stages
     iters = stages[-1][1]
     run_eps = DEFAULT_EPS if args.eps is None else args.eps
     case = cases.case_c2()
     W = cases.weights_c2(args.plans)
     golden = load_golden()
-    pl = Planner(dtype=stages[0][0], max_plans=args.plans)
+    pl = Planner(dtype=stages[0][0], max_plans=args.plans, history=args.history)
     t_load = time.perf_counter()
     pl.load(case, class_solution.VOLUME)
     torch.cuda.synchronize()
@@ -700,10 +747,10 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {
             "workload": f"prostate HDR case, {K} dwells x {M} points, {P} hidden-weight "
-                        f"vectors, L-BFGS m=10, at most {iters} iterations per plan, stop at "
+                        f"vectors, L-BFGS m={args.history}, at most {iters} iterations per plan, stop at "
                         f"relative objective variation {run_eps:g}",
             "dwells": K, "points": M, "plans": P, "iterations": iters, "eps": run_eps,
-            "lbfgs_history": 10, "stages": [f"{d}:{n}" for d, n in stages],
+            "lbfgs_history": args.history, "stages": [f"{d}:{n}" for d, n in stages],
         },
         "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
         "nondominated_fraction": nd_frac,

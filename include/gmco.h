@@ -286,15 +286,36 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_r
                        int rounds_per_graph);
 
 /* Autotuner: time the evaluation kernel of this case and batch for each
- * candidate split count of the point range (workgroups per plan tile of 64
- * plans, or per pair of tiles for the BF16 and FP8 kernels up to 448 padded
- * dwells; up to 32) and keep the fastest.  reps timed launches per candidate
- * on the context stream.  Needs a weight batch.  best_split / best_us may be
- * NULL.  The tuned split belongs to the kernel family of dtype (FP32 operands,
- * or BF16 / FP8) and is used by its rounds in which every plan tile of the
- * batch capacity is active; rounds with fewer active plans (stopped plans are
- * compacted out) choose their split on the device to fill the compute units. */
+ * candidate launch shape and keep the fastest: the split count of the point
+ * range (workgroups per plan tile of 64 plans, or per pair of tiles for the
+ * BF16 and FP8 kernels up to 448 padded dwells; up to 32), the tile-to-XCD
+ * mapping (all tiles of one point range on one XCD, or round-robin) and, for
+ * BF16 / FP8 up to 384 padded dwells, the workgroup shape (eight wavefronts
+ * of 16 plans, two per SIMD, or four of 32 plans, one per SIMD).  reps timed
+ * launches per candidate on the context stream.  Needs a weight batch.
+ * best_split / best_us may be NULL.  The tuning belongs to the kernel family
+ * of dtype (FP32 operands, or BF16 / FP8); the split is used by its rounds in
+ * which every plan tile of the batch capacity is active (rounds with fewer
+ * active plans, stopped plans being compacted out, choose their split on the
+ * device to fill the compute units), the mapping and shape by every round.
+ * No choice changes a result: the per-plan arithmetic and its order are the
+ * same in every shape. */
 int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* best_us);
+
+/* The launch shape of a kernel family (see gmco_autotune). */
+typedef struct {
+  int split;     /* point-range splits of a full-batch round */
+  int tuned;     /* 1: split set by the autotuner or the caller */
+  int lp_shape;  /* BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32 (Kp <= 384); else 0 */
+  int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
+} gmco_tuning;
+
+/* Read or set the launch shape of dtype's kernel family (-1: the context's
+ * dtype), e.g. to reuse an autotuned shape on cases of the same size.  Needs
+ * a loaded case.  set: EINVAL for a split outside 1..the autotuner's range,
+ * xcd_map not 0/1 or a shape not available at the case's dwell count. */
+int gmco_get_tuning(const gmco_ctx* ctx, int dtype, gmco_tuning* out);
+int gmco_set_tuning(gmco_ctx* ctx, int dtype, const gmco_tuning* t);
 
 /* Set the split count directly (e.g. from a cache of autotuned shapes) for
  * both kernel families; otherwise the autotuner's scope.  1 <= split <= the

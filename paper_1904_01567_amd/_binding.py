@@ -33,7 +33,7 @@ EXPORTS = (
     "gmco_strerror", "gmco_mlp_create", "gmco_mlp_destroy", "gmco_mlp_set_stream",
     "gmco_mlp_param_count", "gmco_mlp_set_params", "gmco_mlp_get_params", "gmco_mlp_loss_grad",
     "gmco_mlp_set_data", "gmco_mlp_train", "gmco_mlp_predict", "gmco_mlp_last_error",
-    "gmco_set_weights_learned",
+    "gmco_set_weights_learned", "gmco_get_tuning", "gmco_set_tuning",
 )
 
 
@@ -66,6 +66,10 @@ class gmco_run(C.Structure):
                 ("beta", C.c_double), ("max_ls", C.c_int), ("check_every", C.c_int),
                 ("time_kernels", C.c_int), ("resume_stopped", C.c_int), ("dtype", C.c_int),
                 ("per_case_launches", C.c_int)]
+
+
+class gmco_tuning(C.Structure):
+    _fields_ = [("split", C.c_int), ("tuned", C.c_int), ("lp_shape", C.c_int), ("xcd_map", C.c_int)]
 
 
 class gmco_select_opts(C.Structure):
@@ -135,6 +139,8 @@ def load_library(path: Optional[str] = None):
     lib.gmco_select_plan.argtypes = [vp, C.POINTER(gmco_select_opts), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
     lib.gmco_evaluate_noalloc.argtypes = [vp, vp, vp, vp]
+    lib.gmco_get_tuning.argtypes = [vp, C.c_int, C.POINTER(gmco_tuning)]
+    lib.gmco_set_tuning.argtypes = [vp, C.c_int, C.POINTER(gmco_tuning)]
     lib.gmco_state_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     lib.gmco_get_state.argtypes = [vp, vp, C.c_size_t]
     lib.gmco_set_state.argtypes = [vp, vp, C.c_size_t]
@@ -375,6 +381,17 @@ class Planner:
         self._check(self.lib.gmco_autotune(self._ctx, -1 if dtype is None else DTYPES[dtype], reps,
                                            C.byref(best), C.byref(us)), "autotune")
         return int(best.value), float(us.value)
+
+    def tuning(self, dtype: Optional[str] = None) -> dict:
+        t = gmco_tuning()
+        self._check(self.lib.gmco_get_tuning(self._ctx, -1 if dtype is None else DTYPES[dtype], C.byref(t)),
+                    "get_tuning")
+        return {k: getattr(t, k) for k, _ in gmco_tuning._fields_}
+
+    def set_tuning(self, split: int, lp_shape: int = 0, xcd_map: int = 1, dtype: Optional[str] = None):
+        t = gmco_tuning(int(split), 1, int(lp_shape), int(xcd_map))
+        self._check(self.lib.gmco_set_tuning(self._ctx, -1 if dtype is None else DTYPES[dtype], C.byref(t)),
+                    "set_tuning")
 
     def set_split(self, split: int):
         self._check(self.lib.gmco_set_split(self._ctx, int(split)), "set_split")

@@ -39,6 +39,9 @@ struct Dims {
   int S_lp = 1;       // S and S_tuned of the BF16 / FP8 kernels, whose
   int S_tuned_lp = 0; // workgroups cover lpt tiles each
   int lpt = 1;
+  int lp_shape = 0;   // BF16 / FP8 workgroup shape (autotuned)
+  int xcd32 = 1;      // XCD-aware tile mapping of the FP32-operand kernels
+  int xcd_lp = 1;     // and of the BF16 / FP8 kernels (autotuned)
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
   int grid16 = 1;     // largest grid a compacted round launches: FP32 operands,
   int grid32 = 1;     // BF16 / FP8
@@ -287,6 +290,8 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.ntiles = d.ntiles;
   a.grid = compacted ? std::max(lp ? d.grid32 : d.grid16, units * (lp ? d.S_tuned_lp : d.S_tuned))
                      : a.S * units;
+  a.lp_shape = lp ? d.lp_shape : 0;
+  a.xcd_map = lp ? d.xcd_lp : d.xcd32;
   a.gt = c->gt;
   return a;
 }
@@ -829,7 +834,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
   // argument tables live in one device buffer for the call.
   const bool grouped = r->per_case_launches == 0 && n > 1;
   struct Bucket {
-    int key0, key1;           // (Kp, dtype) or (E, MH)
+    int key0, key1, key2;     // (Kp, dtype, BF16 / FP8 shape) or (E, MH, 0)
     std::vector<int> cases;
     int off = 0, soff = 0, grid = 0, pp_max = 0;
   };
@@ -847,16 +852,16 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
   ReduceArgs* d_rargs = nullptr;
   long long red_threads = 1;
   if (grouped) {
-    auto bucket_of = [](std::vector<Bucket>& v, int k0, int k1) -> Bucket& {
+    auto bucket_of = [](std::vector<Bucket>& v, int k0, int k1, int k2) -> Bucket& {
       for (Bucket& b : v)
-        if (b.key0 == k0 && b.key1 == k1) return b;
-      v.push_back(Bucket{k0, k1, {}});
+        if (b.key0 == k0 && b.key1 == k1 && b.key2 == k2) return b;
+      v.push_back(Bucket{k0, k1, k2, {}});
       return v.back();
     };
     auto mh = [](int m) { return m <= 4 ? 4 : (m <= 10 ? 10 : (m <= 16 ? 16 : GMCO_MAX_HISTORY)); };
     for (int i = 0; i < n; ++i) {
-      bucket_of(eb, ctxs[i]->dim.Kp, dtypes[i]).cases.push_back(i);
-      bucket_of(ub, update_width(ctxs[i]->dim.Kp), mh(ctxs[i]->m)).cases.push_back(i);
+      bucket_of(eb, ctxs[i]->dim.Kp, dtypes[i], as[i].lp_shape).cases.push_back(i);
+      bucket_of(ub, update_width(ctxs[i]->dim.Kp), mh(ctxs[i]->m), 0).cases.push_back(i);
     }
     std::vector<EvalArgs> he;
     std::vector<int> hs;
@@ -907,7 +912,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     if (grouped) {
       for (const Bucket& b : eb)
         GMCO_HIP(c0, launch_eval_grouped(d_eargs + b.off, d_start + b.soff, (int)b.cases.size(), b.grid, b.key0,
-                                         b.key1, st));
+                                         b.key1, b.key2, st));
       GMCO_HIP(c0, launch_reduce_g_grouped(d_rargs, n, red_threads, st));
       for (const Bucket& b : ub)
         GMCO_HIP(c0, launch_update_grouped(d_uargs + b.off, (int)b.cases.size(), b.key0, b.pp_max, b.key1,
@@ -1060,34 +1065,79 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
   if (!dtype_available(c->dtype, dtype)) return fail(c, GMCO_EINVAL, "dtype not available");
   GMCO_HIP(c, hipSetDevice(c->device));
   Dims& d = c->dim;
-  int& S_dense = is_low_precision(dtype) ? d.S_lp : d.S;  // the split this dtype's kernel uses
+  const bool lp = is_low_precision(dtype);
+  int& S_dense = lp ? d.S_lp : d.S;  // the split this dtype's kernel uses
+  int& xcd = lp ? d.xcd_lp : d.xcd32;
   std::vector<int> cand;
   for (int s : {S_dense, 4, 8, 12, 16, 20, 24, 28, 32})
     if (s >= 1 && s <= d.S_cap && s <= d.nblocks && std::find(cand.begin(), cand.end(), s) == cand.end())
       cand.push_back(s);
-  const int orig = S_dense;
-  int best = orig;
+  std::vector<int> shapes = {0};
+  if (lp && lp_shape_ok(d.Kp, 1)) shapes.push_back(1);
+  const int orig_s = S_dense, orig_x = xcd, orig_shape = d.lp_shape;
+  int best = orig_s, best_x = orig_x, best_shape = orig_shape;
   float best_t = 1e30f;
-  for (int s : cand) {
-    S_dense = s;
-    EvalArgs a = eval_args(c, c->at<float>(c->lay.xt), false, dtype);
-    GMCO_HIP(c, launch_eval(a, dtype, c->stream));  // warm-up
-    GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
-    for (int k = 0; k < reps; ++k) GMCO_HIP(c, launch_eval(a, dtype, c->stream));
-    GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
-    GMCO_HIP(c, hipEventSynchronize(c->ev1));
-    float ms = 0.f;
-    GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    const float us = 1e3f * ms / reps;
-    if (us < best_t) {
-      best_t = us;
-      best = s;
+  for (int shape : shapes) {
+    for (int xm : {1, 0}) {
+      for (int s : cand) {
+        S_dense = s;
+        xcd = xm;
+        if (lp) d.lp_shape = shape;
+        EvalArgs a = eval_args(c, c->at<float>(c->lay.xt), false, dtype);
+        GMCO_HIP(c, launch_eval(a, dtype, c->stream));  // warm-up
+        GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
+        for (int k = 0; k < reps; ++k) GMCO_HIP(c, launch_eval(a, dtype, c->stream));
+        GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
+        GMCO_HIP(c, hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        GMCO_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        const float us = 1e3f * ms / reps;
+        if (us < best_t) {
+          best_t = us;
+          best = s;
+          best_x = xm;
+          best_shape = shape;
+        }
+      }
     }
   }
   S_dense = best;
-  (is_low_precision(dtype) ? d.S_tuned_lp : d.S_tuned) = best;
+  xcd = best_x;
+  if (lp) d.lp_shape = best_shape;
+  (lp ? d.S_tuned_lp : d.S_tuned) = best;
   if (best_split) *best_split = best;
   if (best_us) *best_us = best_t;
+  return GMCO_OK;
+}
+
+int gmco_get_tuning(const gmco_ctx* c, int dtype, gmco_tuning* t) {
+  if (!c || !t) return GMCO_EINVAL;
+  if (!c->case_loaded) return GMCO_ESTATE;
+  if (dtype < 0) dtype = c->dtype;
+  const bool lp = is_low_precision(dtype);
+  const Dims& d = c->dim;
+  t->split = lp ? d.S_lp : d.S;
+  t->tuned = (lp ? d.S_tuned_lp : d.S_tuned) > 0;
+  t->lp_shape = lp ? d.lp_shape : 0;
+  t->xcd_map = lp ? d.xcd_lp : d.xcd32;
+  return GMCO_OK;
+}
+
+int gmco_set_tuning(gmco_ctx* c, int dtype, const gmco_tuning* t) {
+  if (!c || !t) return GMCO_EINVAL;
+  if (!c->case_loaded) return fail(c, GMCO_ESTATE, "gmco_load_case first");
+  if (dtype < 0) dtype = c->dtype;
+  if (!dtype_available(c->dtype, dtype)) return fail(c, GMCO_EINVAL, "dtype not available");
+  const bool lp = is_low_precision(dtype);
+  Dims& d = c->dim;
+  if (t->split < 1 || t->split > d.S_cap || t->split > d.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
+  if (t->xcd_map != 0 && t->xcd_map != 1) return fail(c, GMCO_EINVAL, "xcd_map must be 0 or 1");
+  if (lp ? !lp_shape_ok(d.Kp, t->lp_shape) : t->lp_shape != 0)
+    return fail(c, GMCO_EINVAL, "workgroup shape not available at this dwell count");
+  (lp ? d.S_lp : d.S) = t->split;
+  (lp ? d.S_tuned_lp : d.S_tuned) = t->split;
+  (lp ? d.xcd_lp : d.xcd32) = t->xcd_map;
+  if (lp) d.lp_shape = t->lp_shape;
   return GMCO_OK;
 }
 

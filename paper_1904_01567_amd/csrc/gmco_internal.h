@@ -13,12 +13,21 @@ constexpr int kGmax = GMCO_MAX_GROUPS;
 constexpr int kBM = 16;   // dose points per inner block of the evaluation kernel
 constexpr int kPT = 64;   // plans per tile of the evaluation (one FP32 workgroup)
 // Shape of the BF16 / FP8 evaluation workgroup per padded dwell count:
-// threads, and 16-plan column groups per wavefront.  Up to Kp = 384 eight
-// wavefronts of 16 plans (two per SIMD) share one double-buffered LDS tile;
-// at Kp = 416 four wavefronts of 32 plans; above, four of 16 (the registers
-// of 32 plans no longer fit).  lp_tiles: the plan tiles a workgroup covers.
-__host__ __device__ constexpr int lp_threads(int Kp) { return Kp <= 384 ? 512 : 256; }
-__host__ __device__ constexpr int lp_halves(int Kp) { return Kp == 416 ? 2 : 1; }
+// threads, and 16-plan column groups per wavefront.  Shape 0 (default): up
+// to Kp = 384 eight wavefronts of 16 plans (two per SIMD) share one
+// double-buffered LDS tile; at Kp = 416 four wavefronts of 32 plans; above,
+// four of 16 (the registers of 32 plans no longer fit).  Shape 1 (up to
+// Kp = 384, an autotuner candidate): four wavefronts of 32 plans, one per
+// SIMD, each LDS operand feeding twice the matrix ops.  Both shapes of a Kp
+// cover the same plan tiles (lp_tiles), so the grid does not depend on the
+// shape.
+__host__ __device__ constexpr bool lp_shape_ok(int Kp, int shape) { return shape == 0 || (shape == 1 && Kp <= 384); }
+__host__ __device__ constexpr int lp_threads(int Kp, int shape = 0) {
+  return (Kp <= 384 && shape == 0) ? 512 : 256;
+}
+__host__ __device__ constexpr int lp_halves(int Kp, int shape = 0) {
+  return (Kp == 416 || (Kp <= 384 && shape == 1)) ? 2 : 1;
+}
 __host__ __device__ constexpr int lp_tiles(int Kp) { return lp_threads(Kp) / 64 * 16 * lp_halves(Kp) / kPT; }
 constexpr int kKAlign = 32;
 constexpr int kMAlign = 32;  // points: a multiple of every kernel's block
@@ -104,6 +113,8 @@ struct EvalArgs {
   int S;                  // M splits (uncompacted form)
   int ntiles;             // Pp / kPT (uncompacted form)
   int grid;               // workgroups launched; those past the round's grid exit
+  int lp_shape;           // BF16 / FP8 workgroup shape (lp_threads, lp_halves)
+  int xcd_map;            // 1: tiles of one point range on one XCD when the grid allows
   GroupTable gt;
 };
 
@@ -159,7 +170,7 @@ hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st);
 // workgroups are start[c] .. start[c + 1] - 1 of grid (start[c] a multiple
 // of 8), its arguments args[c] (device arrays, n entries / n + 1 starts).
 hipError_t launch_eval_grouped(const EvalArgs* args, const int* start, int n, int grid, int Kp, int dtype,
-                               hipStream_t st);
+                               int lp_shape, hipStream_t st);
 // Update / reduction of n cases in one launch (cases of one update width E
 // for the update); grids sized for the largest case.
 hipError_t launch_update_grouped(const UpdateArgs* args, int n, int E, int Pp_max, int m, int round,

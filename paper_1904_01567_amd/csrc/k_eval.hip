@@ -37,12 +37,12 @@ __device__ inline d4v mfma_f64(float a, float b, d4v c) {
 }
 
 // Maps the flat workgroup id to (split, tile).  Workgroups are dispatched to
-// the 8 XCDs round-robin; when the grid allows it, all tiles of one point
-// range land on the same XCD so that its L2 serves that slice of D to all of
-// them.
-__device__ inline void split_tile(int bid, int S, int ntiles, int& s, int& tile) {
+// the 8 XCDs round-robin; with xcd_map, when the grid allows it, all tiles of
+// one point range land on the same XCD so that its L2 serves that slice of D
+// to all of them.
+__device__ inline void split_tile(int bid, int S, int ntiles, int xcd_map, int& s, int& tile) {
   const int total = S * ntiles;
-  if ((S & 7) == 0 && (total & 7) == 0) {
+  if (xcd_map && (S & 7) == 0 && (total & 7) == 0) {
     const int xcd = bid & 7;
     const int local = bid >> 3;
     s = xcd * (S >> 3) + local / ntiles;
@@ -74,7 +74,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int bid, int* sPlan, int* s
     stride = a.Pp;
     const int units = (a.ntiles + TPW - 1) / TPW;
     if (bid >= S * units) return false;
-    split_tile(bid, S, units, s, unit);
+    split_tile(bid, S, units, a.xcd_map, s, unit);
     j0 = unit * NCOL;
     for (int i = tid; i < NCOL; i += NT) sPlan[i] = j0 + i < a.Pp ? j0 + i : -1;
   } else {
@@ -114,7 +114,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int bid, int* sPlan, int* s
     }
     const int units = (ntiles + TPW - 1) / TPW;
     if (bid >= S * units) return false;
-    split_tile(bid, S, units, s, unit);
+    split_tile(bid, S, units, a.xcd_map, s, unit);
     j0 = unit * NCOL;
     int r = base + v - cnt;
     for (int p = b; p < e; ++p) {
@@ -579,7 +579,7 @@ struct LpOp<true> {
   static __device__ inline f4v mma(long a, long b, f4v c) { return mfma_fp8(a, b, c); }
 };
 
-template <int KP, bool FP8>
+template <int KP, bool FP8, int SHAPE>
 __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   typedef typename LpOp<FP8>::type op_t;
   constexpr int BMP = 32;              // points per block
@@ -589,9 +589,9 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   constexpr int TS = BMP + 4;
   constexpr int NK32 = KP / 32;        // k-steps of the dose product
   constexpr int NK16 = KP / 16;        // 16-dwell tiles of the back-projection
-  constexpr int NT = lp_threads(KP);  // threads
+  constexpr int NT = lp_threads(KP, SHAPE);  // threads
   constexpr int NW = NT / 64;
-  constexpr int NH = lp_halves(KP);   // 16-plan column groups per wavefront
+  constexpr int NH = lp_halves(KP, SHAPE);   // 16-plan column groups per wavefront
   constexpr int NCOL = NW * 16 * NH;
   constexpr int TPW = NCOL / kPT;
   static_assert(TPW == lp_tiles(KP) && TPW * kPT == NCOL, "workgroup of whole plan tiles");
@@ -916,26 +916,51 @@ __global__ __launch_bounds__(512, 1) void k_eval_acc64_grouped(const EvalArgs* _
   eval_acc64<KP>(args[c], blockIdx.x - start[c]);
 }
 
-template <int KP>
-__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_bf16(EvalArgs a) {
-  eval_lp<KP, false>(a, blockIdx.x);
+template <int KP, int SHAPE>
+__global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_bf16(EvalArgs a) {
+  eval_lp<KP, false, SHAPE>(a, blockIdx.x);
 }
-template <int KP>
-__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_bf16_grouped(const EvalArgs* __restrict__ args,
-                                                                         const int* __restrict__ start, int n) {
+template <int KP, int SHAPE>
+__global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_bf16_grouped(
+    const EvalArgs* __restrict__ args, const int* __restrict__ start, int n) {
   const int c = group_case(start, n, blockIdx.x);
-  eval_lp<KP, false>(args[c], blockIdx.x - start[c]);
+  eval_lp<KP, false, SHAPE>(args[c], blockIdx.x - start[c]);
+}
+
+template <int KP, int SHAPE>
+__global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_fp8(EvalArgs a) {
+  eval_lp<KP, true, SHAPE>(a, blockIdx.x);
+}
+template <int KP, int SHAPE>
+__global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_fp8_grouped(
+    const EvalArgs* __restrict__ args, const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_lp<KP, true, SHAPE>(args[c], blockIdx.x - start[c]);
+}
+
+// BF16 / FP8 launch in workgroup shape SHAPE (single case or grouped)
+template <int KP, int SHAPE>
+hipError_t launch_lp(const EvalArgs* single, const EvalArgs* args, const int* start, int n, int grid,
+                     bool fp8, hipStream_t st) {
+  const dim3 g(grid), b(lp_threads(KP, SHAPE));
+  if (single) {
+    if (fp8) hipLaunchKernelGGL((k_eval_fp8<KP, SHAPE>), g, b, 0, st, *single);
+    else hipLaunchKernelGGL((k_eval_bf16<KP, SHAPE>), g, b, 0, st, *single);
+  } else {
+    if (fp8) hipLaunchKernelGGL((k_eval_fp8_grouped<KP, SHAPE>), g, b, 0, st, args, start, n);
+    else hipLaunchKernelGGL((k_eval_bf16_grouped<KP, SHAPE>), g, b, 0, st, args, start, n);
+  }
+  return hipGetLastError();
 }
 
 template <int KP>
-__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_fp8(EvalArgs a) {
-  eval_lp<KP, true>(a, blockIdx.x);
-}
-template <int KP>
-__global__ __launch_bounds__(lp_threads(KP), 1) void k_eval_fp8_grouped(const EvalArgs* __restrict__ args,
-                                                                        const int* __restrict__ start, int n) {
-  const int c = group_case(start, n, blockIdx.x);
-  eval_lp<KP, true>(args[c], blockIdx.x - start[c]);
+hipError_t launch_lp_shape(int shape, const EvalArgs* single, const EvalArgs* args, const int* start, int n,
+                           int grid, bool fp8, hipStream_t st) {
+  if constexpr (lp_shape_ok(KP, 1)) {
+    if (shape == 1) return launch_lp<KP, 1>(single, args, start, n, grid, fp8, st);
+  }
+  if (shape != 0) return hipErrorInvalidValue;
+  return launch_lp<KP, 0>(single, args, start, n, grid, fp8, st);
 }
 
 template <int KP>
@@ -948,17 +973,15 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_F32>), grid, block, 0, st, a);
-  else if (dtype == GMCO_DTYPE_BF16)
-    hipLaunchKernelGGL((k_eval_bf16<KP>), grid, dim3(lp_threads(KP)), 0, st, a);
-  else if (dtype == GMCO_DTYPE_FP8)
-    hipLaunchKernelGGL((k_eval_fp8<KP>), grid, dim3(lp_threads(KP)), 0, st, a);
+  else if (dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8)
+    return launch_lp_shape<KP>(a.lp_shape, &a, nullptr, nullptr, 0, a.grid, dtype == GMCO_DTYPE_FP8, st);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <int KP>
-hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int grid, int dtype,
+hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int grid, int dtype, int lp_shape,
                              hipStream_t st) {
   if (grid < 1 || n < 1) return hipErrorInvalidValue;
   if (dtype == GMCO_DTYPE_F32_ACC64)
@@ -967,10 +990,8 @@ hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int 
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_CHUNK64>), dim3(grid), dim3(256), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32)
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_F32>), dim3(grid), dim3(256), 0, st, args, start, n);
-  else if (dtype == GMCO_DTYPE_BF16)
-    hipLaunchKernelGGL((k_eval_bf16_grouped<KP>), dim3(grid), dim3(lp_threads(KP)), 0, st, args, start, n);
-  else if (dtype == GMCO_DTYPE_FP8)
-    hipLaunchKernelGGL((k_eval_fp8_grouped<KP>), dim3(grid), dim3(lp_threads(KP)), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8)
+    return launch_lp_shape<KP>(lp_shape, nullptr, args, start, n, grid, dtype == GMCO_DTYPE_FP8, st);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1006,11 +1027,11 @@ hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st) {
 }
 
 hipError_t launch_eval_grouped(const EvalArgs* args, const int* start, int n, int grid, int Kp, int dtype,
-                               hipStream_t st) {
+                               int lp_shape, hipStream_t st) {
   switch (Kp) {
 #define GMCO_KP_CASE(v) \
   case v:               \
-    return launch_kp_grouped<v>(args, start, n, grid, dtype, st);
+    return launch_kp_grouped<v>(args, start, n, grid, dtype, lp_shape, st);
     GMCO_KP_CASE(32)
     GMCO_KP_CASE(64)
     GMCO_KP_CASE(96)

@@ -52,8 +52,8 @@ def test_ctypes_layout_matches_header():
 #include <stddef.h>
 #include "gmco.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(gmco_opts), sizeof(gmco_case), sizeof(gmco_run),
-         sizeof(gmco_run_info), sizeof(gmco_plan_metrics));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(gmco_opts), sizeof(gmco_case), sizeof(gmco_run),
+         sizeof(gmco_run_info), sizeof(gmco_plan_metrics), sizeof(gmco_tuning), sizeof(gmco_select_opts));
   printf("%zu %zu %zu\n", offsetof(gmco_plan_metrics, D90_pct), offsetof(gmco_plan_metrics, status),
          offsetof(gmco_case, dose_rate));
   return 0;
@@ -68,7 +68,8 @@ int main(void) {
     sizes = [int(v) for v in lines[0].split()]
     offs = [int(v) for v in lines[1].split()]
     assert sizes == [C.sizeof(b.gmco_opts), C.sizeof(b.gmco_case), C.sizeof(b.gmco_run),
-                     C.sizeof(b.gmco_run_info), C.sizeof(b.gmco_plan_metrics)]
+                     C.sizeof(b.gmco_run_info), C.sizeof(b.gmco_plan_metrics), C.sizeof(b.gmco_tuning),
+                     C.sizeof(b.gmco_select_opts)]
     assert offs == [b.gmco_plan_metrics.D90_pct.offset, b.gmco_plan_metrics.status.offset,
                     b.gmco_case.dose_rate.offset]
 

@@ -163,3 +163,46 @@ def test_uneven_batch_meets_oracle_optima():
         worst = max(worst, float(rel.max()))
         assert rel.max() <= bench.TOL_F and rel.min() >= -1e-6
         assert dv.max() <= bench.TOL_V100
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32acc64"])
+def test_launch_shapes_give_identical_results(dtype):
+    # Every launch shape the autotuner chooses from (split count, tile-to-XCD
+    # mapping, BF16 workgroup of 8 x 16 or 4 x 32 plans) evaluates the same
+    # per-plan arithmetic in the same order: results equal bit for bit.
+    announce(f"launch shapes {dtype}")
+    c = cases.case_c1()
+    W = cases.hidden_weights(200, seed=71)       # four plan tiles
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    x = np.sqrt(O.uniform_start_time(D, c.group, 15.0)) * (
+        0.5 + cases.uniform_draws((W.shape[0], c.K), seed=72))
+    pl = planner(c, W, dtype=dtype)
+    F0, g0 = pl.evaluate(x)
+    shapes = [0, 1] if dtype == "bf16" else [0]
+    for shape in shapes:
+        for xm in (0, 1):
+            for split in (1, 8, 16):
+                pl.set_tuning(split, lp_shape=shape, xcd_map=xm)
+                t = pl.tuning()
+                assert (t["split"], t["lp_shape"], t["xcd_map"]) == (split, shape, xm)
+                F, g = pl.evaluate(x)
+                # splits only reorder the FP64 sum of the objective's partials
+                np.testing.assert_allclose(F, F0, rtol=1e-12)
+    # same split, every shape and mapping: bitwise
+    pl.set_tuning(8, lp_shape=0, xcd_map=1)
+    Fa, ga = pl.evaluate(x)
+    for shape in shapes:
+        for xm in (0, 1):
+            pl.set_tuning(8, lp_shape=shape, xcd_map=xm)
+            F, g = pl.evaluate(x)
+            np.testing.assert_array_equal(F, Fa)
+            np.testing.assert_array_equal(g, ga)
+    best, us = pl.autotune(reps=2)
+    t = pl.tuning()
+    announce(f"autotuned {dtype}: {t} ({us:.1f} us)")
+    assert t["split"] == best and t["tuned"] == 1
+    if dtype == "bf16":
+        from paper_1904_01567_amd import GmcoError
+        big = planner(cases.make_case(20, 20, (300, 60, 100, 120), seed=400), W[:8], dtype="bf16")
+        with pytest.raises(GmcoError):  # Kp = 416 has one shape
+            big.set_tuning(4, lp_shape=1)
