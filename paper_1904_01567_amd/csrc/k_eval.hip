@@ -553,17 +553,27 @@ __device__ inline unsigned pack_fp8x4(float a, float b, float c, float d) {
   return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
 }
 
-// Eq. 1 at dose d for the row pr = (w_min, D_min, D_max, w_max), without
-// branches: with lo = min(d - D_min, 0) and hi = max(d - D_max, 0) (at most
-// one is nonzero since D_min <= D_max) the bracket of eq. 2 is
-// kappa = w_min lo + w_max hi and the penalty kappa (lo + hi).  Adds w times
-// the penalty to f and returns phi = w kappa in BF16.
-__device__ inline __bf16 penalty_lp(float d, float4 pr, float w, double& f) {
-  const float lo = fminf(d - pr.y, 0.f);
-  const float hi = fmaxf(d - pr.z, 0.f);
-  const float kap = pr.x * lo + pr.w * hi;
-  f += (double)(w * (kap * (lo + hi)));
-  return (__bf16)(w * kap);
+// Eq. 1 at dose d for the row pw = (w w_min, D_min, D_max, w w_max), the
+// structure weight w = w_j / N_j folded into the slopes, without branches:
+// with lo = min(d - D_min, 0) and hi = max(d - D_max, 0) (at most one is
+// nonzero since D_min <= D_max) the weighted bracket of eq. 2 is
+// phi = w (w_min lo + w_max hi) and the weighted penalty phi (lo + hi).  Adds
+// the penalty to f (FP32, one block's points; the caller adds f to its FP64
+// sum once per block) and returns phi in BF16.
+__device__ inline __bf16 penalty_lp(float d, float4 pw, float& f) {
+  const float lo = fminf(d - pw.y, 0.f);
+  const float hi = fmaxf(d - pw.z, 0.f);
+  const float phi = pw.x * lo + pw.w * hi;
+  f = fmaf(phi, lo + hi, f);
+  return (__bf16)phi;
+}
+
+// Position of point r of a 32-point block in a dwell row of the transposed
+// tile: the 8 contraction slots lane quad q supplies to the back-projection
+// (the dose product's rows 4q .. 4q+3 and 16+4q .. 16+4q+3) are positions
+// 8q .. 8q+7, so each lane reads its operand as one 16-byte access.
+__host__ __device__ constexpr int tpos(int r) {
+  return r < 16 ? 8 * (r >> 2) + (r & 3) : 8 * ((r - 16) >> 2) + 4 + ((r - 16) & 3);
 }
 
 template <bool FP8>
@@ -583,10 +593,16 @@ template <int KP, bool FP8, int SHAPE>
 __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   typedef typename LpOp<FP8>::type op_t;
   constexpr int BMP = 32;              // points per block
-  // D tile row stride (BF16 elements or FP8 bytes) and transposed tile row
-  // stride, chosen by timing the layouts (unpadded rows are 1.6-2.3x slower)
+  // D tile row stride (BF16 elements or FP8 bytes), chosen by timing the
+  // layouts (unpadded rows are 1.6-2.3x slower; KP + 8 for BF16 measured no
+  // better than KP + 16)
   constexpr int DS = FP8 ? KP + 8 : KP + 16;
-  constexpr int TS = BMP + 4;
+  // Transposed tile: dwell row l starts at trow(l) = l TS BF16 elements;
+  // 80-byte rows keep every operand read one aligned 16-byte access.  (Rows
+  // skewed by 64 bytes every 8 or 16 dwells, meant to separate the staging
+  // writes' banks, measured more bank conflicts and 8 % longer launches.)
+  constexpr int TS = BMP + 8;
+  constexpr int TSZ = KP * TS;
   constexpr int NK32 = KP / 32;        // k-steps of the dose product
   constexpr int NK16 = KP / 16;        // 16-dwell tiles of the back-projection
   constexpr int NT = lp_threads(KP, SHAPE);  // threads
@@ -609,7 +625,8 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
 
   // two buffers: block b is read from one while block b + 1 is staged in the other
   __shared__ __attribute__((aligned(16))) unsigned char sD[2][SDB];
-  __shared__ __attribute__((aligned(16))) __bf16 sT[2][KP * TS];
+  __shared__ __attribute__((aligned(16))) __bf16 sT[2][TSZ];
+  auto trow = [](int l) { return l * TS; };
   __shared__ int sG[2][BMP];
   __shared__ float sW[NCOL * kGmax];
   __shared__ int sPlan[NCOL];
@@ -738,7 +755,8 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
           *reinterpret_cast<u4v*>(&sD16[(2 * rp) * DS + 8 * c8]) = p0[i];
           *reinterpret_cast<u4v*>(&sD16[(2 * rp + 1) * DS + 8 * c8]) = p1[i];
           // word (dwell 8 c8 + e, points 2 rp .. 2 rp + 1) of the transposed tile
-          unsigned* dst = sT32 + (8 * c8) * (TS / 2) + rp;
+          // points 2 rp, 2 rp + 1 sit at positions tpos(2 rp), tpos(2 rp) + 1
+          unsigned* dst = sT32 + (trow(8 * c8) >> 1) + (tpos(2 * rp) >> 1);
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
             // low halves of both rows, then high halves (byte selects of v_perm)
@@ -763,7 +781,7 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
         const int c = tid + NT * i;
         if (NCH % NT == 0 || c < NCH) {
           const int l = c >> 2, part = c & 3;
-          u2v* dst = reinterpret_cast<u2v*>(&sT[buf][l * TS + part * 8]);
+          u2v* dst = reinterpret_cast<u2v*>(&sT[buf][trow(l) + part * 8]);
           dst[0] = u2v{pt[i][0], pt[i][1]};
           dst[1] = u2v{pt[i][2], pt[i][3]};
         }
@@ -788,6 +806,7 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
     const int cur = (b - b_begin) & 1;
     const unsigned char* cD = sD[cur];
     const __bf16* cT = sT[cur];
+    const int tbase = trow(n) + 8 * q;
     const int* cG = sG[cur];
 
     // ---- dose product for the two 16-point row tiles ----
@@ -816,20 +835,25 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
     // single structure: then the eq. 1 row and the weight w_j / N_j are the
     // same for all points of the block and are read once.
     bf8v phi[NH];
+    float fblk[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) fblk[h] = 0.f;
     const int g0 = cG[0];
     if (__all(cG[lane & (BMP - 1)] == g0)) {
       const float4 pr = sP[g0];
-      float w[NH];
+      float4 pw[NH];
 #pragma unroll
-      for (int h = 0; h < NH; ++h)
-        w[h] = g0 < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + g0] : 0.f;
+      for (int h = 0; h < NH; ++h) {
+        const float w = g0 < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + g0] : 0.f;
+        pw[h] = make_float4(w * pr.x, pr.y, pr.z, w * pr.w);
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e)
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
           float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
           if constexpr (FP8) d *= u[h];
-          phi[h][e] = penalty_lp(d, pr, w[h], facc[h]);
+          phi[h][e] = penalty_lp(d, pw[h], fblk[h]);
         }
     } else {
 #pragma unroll
@@ -841,16 +865,16 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
           float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
           if constexpr (FP8) d *= u[h];
           const float w = gi < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + gi] : 0.f;
-          phi[h][e] = penalty_lp(d, pr, w, facc[h]);
+          phi[h][e] = penalty_lp(d, make_float4(w * pr.x, pr.y, pr.z, w * pr.w), fblk[h]);
         }
       }
     }
+#pragma unroll
+    for (int h = 0; h < NH; ++h) facc[h] += (double)fblk[h];
     // ---- back-projection over the 32 points ----
 #pragma unroll
     for (int k = 0; k < NK16; ++k) {
-      const bf4v lo = *reinterpret_cast<const bf4v*>(&cT[(16 * k + n) * TS + 4 * q]);
-      const bf4v hi = *reinterpret_cast<const bf4v*>(&cT[(16 * k + n) * TS + 16 + 4 * q]);
-      const bf8v av = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      const bf8v av = *reinterpret_cast<const bf8v*>(&cT[tbase + k * 16 * TS]);
 #pragma unroll
       for (int h = 0; h < NH; ++h) gacc[h][k] = mfma_bf16(av, phi[h], gacc[h][k]);
     }

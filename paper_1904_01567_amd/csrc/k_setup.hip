@@ -74,8 +74,16 @@ __global__ void k_colscale(const double* __restrict__ D64, int Mp, int Kp, float
   if (threadIdx.x == 0) cs[l] = red[0] > 0.0 ? (float)(red[0] / 224.0) : 1.f;
 }
 
+// Position of point r of a 32-point block in the FP8 evaluation's transposed
+// tile (its back-projection operand order): rows 4q .. 4q+3 and
+// 16+4q .. 16+4q+3 of the block at positions 8q .. 8q+7.
+__device__ inline int tpos32(int r) {
+  return r < 16 ? 8 * (r >> 2) + (r & 3) : 8 * ((r - 16) >> 2) + 4 + ((r - 16) & 3);
+}
+
 // FP8 (hardware e4m3 encoding) copy of D_il / s_l, row-major, and the BF16
-// dwell-major copy for the back-projection.
+// dwell-major copy for the back-projection, its points in the tile order of
+// each 32-point block (Mp is a multiple of 32).
 __global__ void k_cast_fp8(const double* __restrict__ D64, int Mp, int Kp,
                            const float* __restrict__ cs, unsigned char* __restrict__ D8,
                            uint16_t* __restrict__ DT) {
@@ -85,7 +93,7 @@ __global__ void k_cast_fp8(const double* __restrict__ D64, int Mp, int Kp,
     const size_t i = idx / Kp, l = idx - i * Kp;
     const float v = (float)D64[idx];
     D8[idx] = (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(v / cs[l], 0.f, 0, false) & 0xff);
-    DT[l * Mp + i] = bf16_rne(v);
+    DT[l * Mp + (i & ~(size_t)31) + tpos32((int)(i & 31))] = bf16_rne(v);
   }
 }
 
