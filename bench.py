@@ -177,8 +177,8 @@ def cpu_baseline(n_plans: int, max_iter: int, eps: float, n_batch: int = 1000):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return dict(value=n_plans / t, unit="plans/s", cores=int(threads), kind="oracle",
                 host_cpu=host_cpu_model(), host_logical_cpus=os.cpu_count(),
-                sample=f"{n_plans} of the {n_batch} weight vectors (every "
-                       f"{max(1, n_batch // n_plans)}th) of the 360-dwell / 20,000-point case, each "
+                sample=f"{n_plans} of the {n_batch} weight vectors (spread evenly over the batch) "
+                       f"of the 360-dwell / 20,000-point case, each "
                        f"run to its own stop (relative objective variation {eps:g}, at most "
                        f"{max_iter} steps; {int(np.sum(r['iters']))} accepted steps in all, "
                        f"median {int(np.median(r['iters']))}) in {t:.1f} s (FP64 NumPy, BLAS "
