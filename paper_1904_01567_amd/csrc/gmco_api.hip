@@ -713,19 +713,24 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   a_timed.work2 = work + 1;
   const int check = r->check_every > 0 ? r->check_every : 16;
   const long long max_rounds = 1 + (long long)std::max(r->max_iter, 1) * r->max_ls + 1;
-  // optional sampled timing: events around the evaluation and the update of
-  // every time_kernels-th round, 4 per timed round of one check block
+  // Rounds are issued in blocks of `check`.  After each block the running-plan
+  // count is copied to pinned host memory and an event recorded; the host
+  // then waits for the block before last, so the device always has the next
+  // block queued and never idles at a check.  When a block reports no running
+  // plan, the one queued after it runs as empty rounds (every kernel exits at
+  // once) and is not timed.
+  // Optional sampled timing: events around the evaluation and the update of
+  // every time_kernels-th round, 4 per timed round, one set per block parity.
   const int every = r->time_kernels;
   std::vector<hipEvent_t> ev;
+  hipEvent_t bev[2] = {nullptr, nullptr};
   int timed = 0;
-  if (every > 0) {
-    ev.resize((size_t)4 * check, nullptr);
-    for (auto& e : ev) {
-      if (hipEventCreate(&e) != hipSuccess) {
-        for (auto& f : ev)
-          if (f) hipEventDestroy(f);
-        return fail(c, GMCO_EHIP, "hipEventCreate failed");
-      }
+  ev.resize((every > 0 ? (size_t)8 * check : 0) + 2, nullptr);
+  for (auto& e : ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : ev)
+        if (f) hipEventDestroy(f);
+      return fail(c, GMCO_EHIP, "hipEventCreate failed");
     }
   }
   struct EventGuard {
@@ -735,15 +740,20 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
         if (e) hipEventDestroy(e);
     }
   } guard{ev};
+  bev[0] = ev[ev.size() - 2];
+  bev[1] = ev[ev.size() - 1];
   double eval_ms = 0.0, update_ms = 0.0;
-  auto harvest = [&](int n) -> hipError_t {
+  int in_block[2] = {0, 0};
+  auto harvest = [&](int set) -> hipError_t {
+    const int n = in_block[set];
+    hipEvent_t* e = ev.data() + (size_t)set * 4 * check;
     timed += n;
     for (int i = 0; i < n; ++i) {
       float a_ms = 0.f, b_ms = 0.f;
-      hipError_t e = hipEventElapsedTime(&a_ms, ev[4 * i], ev[4 * i + 1]);
-      if (e != hipSuccess) return e;
-      e = hipEventElapsedTime(&b_ms, ev[4 * i + 2], ev[4 * i + 3]);
-      if (e != hipSuccess) return e;
+      hipError_t er = hipEventElapsedTime(&a_ms, e[4 * i], e[4 * i + 1]);
+      if (er != hipSuccess) return er;
+      er = hipEventElapsedTime(&b_ms, e[4 * i + 2], e[4 * i + 3]);
+      if (er != hipSuccess) return er;
       eval_ms += a_ms;
       update_ms += b_ms;
     }
@@ -751,36 +761,56 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   };
   GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
   long long round = 0;
-  int in_block = 0;
-  for (; round < max_rounds; ++round) {
-    u.round = (int)round;
-    const bool tk = every > 0 && round % every == 0;
-    if (tk) GMCO_HIP(c, hipEventRecord(ev[4 * in_block], c->stream));
-    GMCO_HIP(c, launch_eval(tk ? a_timed : a, dtype, c->stream));
-    if (tk) {
-      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 1], c->stream));
-      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 2], c->stream));
+  long long blk = 0;  // blocks issued
+  bool done_flag = false;
+  while (!done_flag) {
+    const int set = (int)(blk & 1);
+    hipEvent_t* e = every > 0 ? ev.data() + (size_t)set * 4 * check : nullptr;
+    in_block[set] = 0;
+    for (int k = 0; k < check && round < max_rounds; ++k, ++round) {
+      u.round = (int)round;
+      const bool tk = every > 0 && round % every == 0;
+      const int i = in_block[set];
+      if (tk) GMCO_HIP(c, hipEventRecord(e[4 * i], c->stream));
+      GMCO_HIP(c, launch_eval(tk ? a_timed : a, dtype, c->stream));
+      if (tk) {
+        GMCO_HIP(c, hipEventRecord(e[4 * i + 1], c->stream));
+        GMCO_HIP(c, hipEventRecord(e[4 * i + 2], c->stream));
+      }
+      GMCO_HIP(c, launch_reduce_g(a.Gpart, a.rt, d.Pp, d.Kp, c->at<float>(L.Gsum), c->stream));
+      GMCO_HIP(c, launch_update(u, c->stream));
+      if (tk) {
+        GMCO_HIP(c, hipEventRecord(e[4 * i + 3], c->stream));
+        ++in_block[set];
+      }
     }
-    GMCO_HIP(c, launch_reduce_g(a.Gpart, a.rt, d.Pp, d.Kp, c->at<float>(L.Gsum), c->stream));
-    GMCO_HIP(c, launch_update(u, c->stream));
-    if (tk) {
-      GMCO_HIP(c, hipEventRecord(ev[4 * in_block + 3], c->stream));
-      ++in_block;
-    }
-    if ((round + 1) % check == 0) {
-      GMCO_HIP(c, hipMemcpyAsync(c->host_count, active + (round & 1), sizeof(int), hipMemcpyDeviceToHost, c->stream));
-      GMCO_HIP(c, hipStreamSynchronize(c->stream));
-      if (every > 0) GMCO_HIP(c, harvest(in_block));
-      in_block = 0;
-      if (*c->host_count == 0) {
-        ++round;
-        break;
+    // running plans after this block's last round (the next update resets the
+    // other counter, so the copy is queued before any later round)
+    GMCO_HIP(c, hipMemcpyAsync(c->host_count + set, active + ((round - 1) & 1), sizeof(int),
+                               hipMemcpyDeviceToHost, c->stream));
+    GMCO_HIP(c, hipEventRecord(bev[set], c->stream));
+    ++blk;
+    if (round >= max_rounds) {  // nothing more to issue: wait for the last block
+      GMCO_HIP(c, hipEventSynchronize(bev[set]));
+      // the block before it is not harvested yet; the last block ran empty
+      // when that one already reported no running plan
+      const bool last_empty = blk >= 2 && c->host_count[set ^ 1] == 0;
+      if (every > 0 && blk >= 2) GMCO_HIP(c, harvest(set ^ 1));
+      if (every > 0 && !last_empty) GMCO_HIP(c, harvest(set));
+      done_flag = true;
+    } else if (blk >= 2) {  // wait for the block before this one
+      const int prev = set ^ 1;
+      GMCO_HIP(c, hipEventSynchronize(bev[prev]));
+      if (every > 0) GMCO_HIP(c, harvest(prev));
+      if (c->host_count[prev] == 0) {
+        // the block just queued runs empty: wait for it, do not time it
+        GMCO_HIP(c, hipEventSynchronize(bev[set]));
+        done_flag = true;
       }
     }
   }
   GMCO_HIP(c, hipEventRecord(c->ev1, c->stream));
   GMCO_HIP(c, hipEventSynchronize(c->ev1));
-  if (every > 0) GMCO_HIP(c, harvest(in_block));
   unsigned long long done[2] = {0, 0};
   GMCO_HIP(c, hipMemcpy(done, work, sizeof(done), hipMemcpyDeviceToHost));
   float ms = 0.f;
@@ -927,25 +957,63 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     }
     return GMCO_OK;
   };
-  auto all_done = [&](long long last_round) -> int {  // 1 done, 0 not, < 0 error
+  // After each block of rounds the running-plan counts go to pinned host
+  // memory (slot = block parity) with an event; the host waits for the block
+  // before last, so the next block is always queued (as in gmco_optimize).
+  hipEvent_t bev[2] = {nullptr, nullptr};
+  struct BevGuard {
+    hipEvent_t* e;
+    ~BevGuard() {
+      for (int k = 0; k < 2; ++k)
+        if (e[k]) hipEventDestroy(e[k]);
+    }
+  } bev_guard{bev};
+  for (int k = 0; k < 2; ++k)
+    GMCO_HIP(c0, hipEventCreateWithFlags(&bev[k], hipEventDisableTiming));
+  auto post_counts = [&](int slot, long long last_round) -> int {
     for (int i = 0; i < n; ++i)
-      GMCO_HIP(ctxs[i], hipMemcpyAsync(ctxs[i]->host_count, ctxs[i]->at<int>(ctxs[i]->lay.active) + (last_round & 1),
-                                       sizeof(int), hipMemcpyDeviceToHost, st));
-    GMCO_HIP(c0, hipStreamSynchronize(st));
+      GMCO_HIP(ctxs[i], hipMemcpyAsync(ctxs[i]->host_count + slot,
+                                       ctxs[i]->at<int>(ctxs[i]->lay.active) + (last_round & 1), sizeof(int),
+                                       hipMemcpyDeviceToHost, st));
+    GMCO_HIP(c0, hipEventRecord(bev[slot], st));
+    return GMCO_OK;
+  };
+  auto all_done = [&](int slot) -> int {  // 1 done, 0 not, < 0 error
+    GMCO_HIP(c0, hipEventSynchronize(bev[slot]));
     long long tot = 0;
-    for (int i = 0; i < n; ++i) tot += *ctxs[i]->host_count;
+    for (int i = 0; i < n; ++i) tot += ctxs[i]->host_count[slot];
     return tot == 0 ? 1 : 0;
+  };
+  // one block issued: post its counts, then decide on the block before it
+  long long blk = 0;
+  auto after_block = [&](long long last_round, bool at_max) -> int {  // 1 stop, 0 go on
+    const int slot = (int)(blk & 1);
+    int rc2 = post_counts(slot, last_round);
+    if (rc2) return rc2;
+    ++blk;
+    if (at_max) {
+      GMCO_HIP(c0, hipEventSynchronize(bev[slot]));
+      return 1;
+    }
+    if (blk < 2) return 0;
+    const int dn = all_done(slot ^ 1);
+    if (dn < 0) return dn;
+    if (dn) {  // the block just queued runs empty
+      GMCO_HIP(c0, hipEventSynchronize(bev[slot]));
+      return 1;
+    }
+    return 0;
   };
   GMCO_HIP(c0, hipEventRecord(c0->ev0, st));
   long long round = 0;
   if (R == 0) {
     const int check = r->check_every > 0 ? r->check_every : 16;
-    while (round < max_rounds) {
+    while (true) {
       int rc = issue_round(round);
       if (rc) return rc;
       ++round;
-      if (round % check == 0) {
-        const int dn = all_done(round - 1);
+      if (round % check == 0 || round >= max_rounds) {
+        const int dn = after_block(round - 1, round >= max_rounds);
         if (dn < 0) return dn;
         if (dn) break;
       }
@@ -971,10 +1039,10 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
       hipGraphExec_t e;
       ~ExecGuard() { hipGraphExecDestroy(e); }
     } eg{exec};
-    while (round < max_rounds) {
+    while (true) {
       GMCO_HIP(c0, hipGraphLaunch(exec, st));
       round += R;
-      const int dn = all_done(R - 1);
+      const int dn = after_block(R - 1, round >= max_rounds);
       if (dn < 0) return dn;
       if (dn) break;
     }

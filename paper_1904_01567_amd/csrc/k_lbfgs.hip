@@ -142,20 +142,20 @@ __device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
   const int m = a.m;
   const size_t row = (size_t)p * Kp;
 
-  // Everything that does not depend on the plan's state is loaded together
-  // with it (the round's shape, the plan's compact column and its vectors),
-  // so that the kernel waits on two levels of loads, not three.  For a
-  // stopped plan the values are not used.
+  // Two levels of loads: first the plan's state with the round's shape and
+  // the plan's compact column (small, recently written), then, for a running
+  // plan only, its vectors, history and gradient sums all at once.  A
+  // stopped plan costs one 64-byte read.
   PlanState st = a.ps[p];
   const RoundTable rt = *a.rt;
   const size_t col = (size_t)a.slot[p];
+  if (!state_active(st.status)) return;
   float xt[E], gt[E], x[E], g[E], d[E];
   float G[E];
   load_vec(a.xt + row, lane, Kp, xt);
   load_vec(a.x + row, lane, Kp, x);
   load_vec(a.g + row, lane, Kp, g);
   load_vec(a.dir + row, lane, Kp, d);
-  if (!state_active(st.status)) return;
 
   // ---- objective and gradient at the evaluated point ----
   // The stored history pairs in age order (0 = newest before this round),
