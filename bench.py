@@ -570,6 +570,9 @@ def main(argv=None) -> int:
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
     ap.add_argument("--history", type=int, default=10, help="L-BFGS pairs m")
+    ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1],
+                    help="workgroup shape of the FP64-accumulated kernel (0: 512 threads per "
+                         "64 plans, 1: 256 threads per 32 plans); default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-plans", type=int, default=16,
                     help="plans of the oracle's host timing, spread over the batch")
@@ -670,6 +673,9 @@ def main(argv=None) -> int:
     pl.load(case, class_solution.VOLUME)
     torch.cuda.synchronize()
     t_load = time.perf_counter() - t_load
+    if args.acc_shape is not None:
+        t = pl.tuning("f32acc64")
+        pl.set_tuning(t["split"], lp_shape=args.acc_shape, xcd_map=t["xcd_map"], dtype="f32acc64")
 
     if args.calibrate:
         # the run's stages from the start, the last one capped at n accepted
@@ -764,6 +770,7 @@ def main(argv=None) -> int:
             "rounds_per_stage": [sum(i["stages"][k]["rounds"] for i in infos) / args.steps
                                  for k in range(len(stages))],
             "load_case_once_ms": 1e3 * t_load,
+            "acc64_workgroup_shape": pl.tuning("f32acc64")["lp_shape"],
         },
         "roofline": {
             "bound": "mfma",

@@ -306,14 +306,19 @@ int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* be
 typedef struct {
   int split;     /* point-range splits of a full-batch round */
   int tuned;     /* 1: split set by the autotuner or the caller */
-  int lp_shape;  /* BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32 (Kp <= 384); else 0 */
+  int lp_shape;  /* workgroup shape.  BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32
+                    (Kp <= 384).  FP32 operands with FP64-accumulated dose: 0 = 512
+                    threads per 64-plan tile, 1 = 256 threads per 32 plans (two
+                    workgroups per compute unit).  Plain FP32: 0 */
   int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
 } gmco_tuning;
 
 /* Read or set the launch shape of dtype's kernel family (-1: the context's
  * dtype), e.g. to reuse an autotuned shape on cases of the same size.  Needs
  * a loaded case.  set: EINVAL for a split outside 1..the autotuner's range,
- * xcd_map not 0/1 or a shape not available at the case's dwell count. */
+ * xcd_map not 0/1 or a shape not available for dtype at the case's dwell
+ * count.  The FP32-operand kernels share split and mapping; the shape is
+ * the FP64-accumulated kernel's. */
 int gmco_get_tuning(const gmco_ctx* ctx, int dtype, gmco_tuning* out);
 int gmco_set_tuning(gmco_ctx* ctx, int dtype, const gmco_tuning* t);
 

@@ -40,6 +40,8 @@ struct Dims {
   int S_tuned_lp = 0; // workgroups cover lpt tiles each
   int lpt = 1;
   int lp_shape = 0;   // BF16 / FP8 workgroup shape (autotuned)
+  int acc_shape = 0;  // FP64-accumulated kernel: 0 = 512 threads per plan tile,
+                      // 1 = 256 threads per half tile (autotuned)
   int xcd32 = 1;      // XCD-aware tile mapping of the FP32-operand kernels
   int xcd_lp = 1;     // and of the BF16 / FP8 kernels (autotuned)
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
@@ -172,6 +174,16 @@ Dims make_dims(int M, int K, int Pmax, int n_cu, int Md) {
   return d;
 }
 
+// Workgroup shape of the evaluation kernel of `dtype`, and its workgroups
+// per split at the full plan capacity.
+int eval_shape(const Dims& d, int dtype) {
+  return is_low_precision(dtype) ? d.lp_shape : (dtype == GMCO_DTYPE_F32_ACC64 ? d.acc_shape : 0);
+}
+int eval_units(const Dims& d, int dtype) {
+  if (is_low_precision(dtype)) return (d.ntiles + d.lpt - 1) / d.lpt;
+  return (dtype == GMCO_DTYPE_F32_ACC64 && d.acc_shape == 1) ? 2 * d.ntiles : d.ntiles;
+}
+
 Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   Layout L{};
   size_t off = 0;
@@ -270,7 +282,7 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.wn = c->at<float>(c->lay.wn);
   const Dims& d = c->dim;
   const bool lp = is_low_precision(dtype);
-  const int units = lp ? (d.ntiles + d.lpt - 1) / d.lpt : d.ntiles;
+  const int units = eval_units(d, dtype);
   if (compacted) {
     a.flag = c->at<int>(c->lay.flag);
     a.split_tab = c->at<int>(c->lay.split_tab) + (is_low_precision(dtype) ? c->dim.ntiles + 1 : 0);
@@ -288,9 +300,10 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.nblocks = c->dim.nblocks;
   a.S = lp ? d.S_lp : d.S;
   a.ntiles = d.ntiles;
-  a.grid = compacted ? std::max(lp ? d.grid32 : d.grid16, units * (lp ? d.S_tuned_lp : d.S_tuned))
-                     : a.S * units;
-  a.lp_shape = lp ? d.lp_shape : 0;
+  // a half-tile workgroup doubles the grid of every split
+  const int grid_max = lp ? d.grid32 : d.grid16 * (units / d.ntiles);
+  a.grid = compacted ? std::max(grid_max, units * (lp ? d.S_tuned_lp : d.S_tuned)) : a.S * units;
+  a.lp_shape = eval_shape(d, dtype);
   a.xcd_map = lp ? d.xcd_lp : d.xcd32;
   a.gt = c->gt;
   return a;
@@ -1099,7 +1112,7 @@ int gmco_evaluate_noalloc(gmco_ctx* c, const double* x_dev, double* F_dev, doubl
   if (!c->case_loaded || c->P == 0) return fail(c, GMCO_ESTATE, "gmco_set_weights first");
   const Dims& d = c->dim;
   const bool lp = is_low_precision(c->dtype);
-  const int units = lp ? (d.ntiles + d.lpt - 1) / d.lpt : d.ntiles;
+  const int units = eval_units(d, c->dtype);
   const size_t PK = (size_t)d.Pp * d.Kp;
   const size_t xe_bytes = align256(PK * 4);
   const size_t per_split = align256(PK * 4) + align256((size_t)d.Pp * 8);
@@ -1141,8 +1154,9 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
     if (s >= 1 && s <= d.S_cap && s <= d.nblocks && std::find(cand.begin(), cand.end(), s) == cand.end())
       cand.push_back(s);
   std::vector<int> shapes = {0};
-  if (lp && lp_shape_ok(d.Kp, 1)) shapes.push_back(1);
-  const int orig_s = S_dense, orig_x = xcd, orig_shape = d.lp_shape;
+  if ((lp && lp_shape_ok(d.Kp, 1)) || dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(1);
+  int& shape_ref = lp ? d.lp_shape : d.acc_shape;  // (unused by the plain FP32 kernel)
+  const int orig_s = S_dense, orig_x = xcd, orig_shape = shape_ref;
   int best = orig_s, best_x = orig_x, best_shape = orig_shape;
   float best_t = 1e30f;
   for (int shape : shapes) {
@@ -1150,7 +1164,7 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
       for (int s : cand) {
         S_dense = s;
         xcd = xm;
-        if (lp) d.lp_shape = shape;
+        shape_ref = shape;
         EvalArgs a = eval_args(c, c->at<float>(c->lay.xt), false, dtype);
         GMCO_HIP(c, launch_eval(a, dtype, c->stream));  // warm-up
         GMCO_HIP(c, hipEventRecord(c->ev0, c->stream));
@@ -1171,7 +1185,7 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
   }
   S_dense = best;
   xcd = best_x;
-  if (lp) d.lp_shape = best_shape;
+  shape_ref = best_shape;
   (lp ? d.S_tuned_lp : d.S_tuned) = best;
   if (best_split) *best_split = best;
   if (best_us) *best_us = best_t;
@@ -1186,7 +1200,7 @@ int gmco_get_tuning(const gmco_ctx* c, int dtype, gmco_tuning* t) {
   const Dims& d = c->dim;
   t->split = lp ? d.S_lp : d.S;
   t->tuned = (lp ? d.S_tuned_lp : d.S_tuned) > 0;
-  t->lp_shape = lp ? d.lp_shape : 0;
+  t->lp_shape = eval_shape(d, dtype);
   t->xcd_map = lp ? d.xcd_lp : d.xcd32;
   return GMCO_OK;
 }
@@ -1200,12 +1214,14 @@ int gmco_set_tuning(gmco_ctx* c, int dtype, const gmco_tuning* t) {
   Dims& d = c->dim;
   if (t->split < 1 || t->split > d.S_cap || t->split > d.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
   if (t->xcd_map != 0 && t->xcd_map != 1) return fail(c, GMCO_EINVAL, "xcd_map must be 0 or 1");
-  if (lp ? !lp_shape_ok(d.Kp, t->lp_shape) : t->lp_shape != 0)
-    return fail(c, GMCO_EINVAL, "workgroup shape not available at this dwell count");
+  if (lp ? !lp_shape_ok(d.Kp, t->lp_shape)
+         : (t->lp_shape != 0 && !(dtype == GMCO_DTYPE_F32_ACC64 && t->lp_shape == 1)))
+    return fail(c, GMCO_EINVAL, "workgroup shape not available for this dtype / dwell count");
   (lp ? d.S_lp : d.S) = t->split;
   (lp ? d.S_tuned_lp : d.S_tuned) = t->split;
   (lp ? d.xcd_lp : d.xcd32) = t->xcd_map;
   if (lp) d.lp_shape = t->lp_shape;
+  else if (dtype == GMCO_DTYPE_F32_ACC64) d.acc_shape = t->lp_shape;
   return GMCO_OK;
 }
 

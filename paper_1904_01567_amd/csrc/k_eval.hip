@@ -59,20 +59,21 @@ __device__ inline void split_tile(int bid, int S, int ntiles, int xcd_map, int& 
 // columns' structure weights.  In a compacted round every workgroup ranks
 // the running plans itself (a block-wide scan of the flags), so no separate
 // launch is needed.  Returns false, for the whole workgroup, when the grid
-// is larger than this round's S * ceil(ntiles / TPW).  Columns at or past
-// `stride` (the second tile of the last workgroup when ntiles is odd) are
-// empty and have no partials.
-template <int NT, int TPW = 1>
+// is larger than this round's S * (units of NCOL columns).  A workgroup
+// covers NCOL consecutive columns: TPW whole plan tiles (NCOL = TPW kPT) or
+// half a tile (NCOL = kPT / 2).  Columns at or past `stride` (the second tile
+// of the last workgroup when ntiles is odd) are empty and have no partials.
+template <int NT, int NCOL = kPT>
 __device__ inline bool tile_setup(const EvalArgs& a, int bid, int* sPlan, int* sScan, float* sW, int& s,
                                   int& S, int& stride, int& j0) {
-  constexpr int NCOL = TPW * kPT;
+  static_assert(NCOL % 16 == 0 && (NCOL % kPT == 0 || kPT % NCOL == 0), "whole 16-plan groups");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int unit;
   if (a.flag == nullptr) {
     S = a.S;
     stride = a.Pp;
-    const int units = (a.ntiles + TPW - 1) / TPW;
+    const int units = (a.ntiles * kPT + NCOL - 1) / NCOL;
     if (bid >= S * units) return false;
     split_tile(bid, S, units, a.xcd_map, s, unit);
     j0 = unit * NCOL;
@@ -112,7 +113,7 @@ __device__ inline bool tile_setup(const EvalArgs& a, int bid, int* sPlan, int* s
       if (a.work != nullptr) *a.work += (unsigned long long)nact;
       if (a.work2 != nullptr) *a.work2 += (unsigned long long)nact;
     }
-    const int units = (ntiles + TPW - 1) / TPW;
+    const int units = (ntiles * kPT + NCOL - 1) / NCOL;
     if (bid >= S * units) return false;
     split_tile(bid, S, units, a.xcd_map, s, unit);
     j0 = unit * NCOL;
@@ -345,20 +346,26 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
 // q = 0, 1, and the swizzle keeps the dose product's float4 reads of rows
 // 0..15 conflict-free.
 // ---------------------------------------------------------------------------
-template <int KP>
+// NG plan groups of 16 per workgroup: NG = 4 (512 threads, one workgroup of
+// 64 plans per CU) or NG = 2 (256 threads, 32 plans, half a tile; two
+// workgroups per CU whose barriers and eq. 1 phases are independent, so one
+// can run its matrix ops while the other waits).  Per plan the arithmetic
+// and its order are the same in both.
+template <int KP, int NG>
 __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
-  constexpr int NT = 512;
+  constexpr int NT = 128 * NG;
+  constexpr int NCOL = 16 * NG;
   constexpr int KS = KP + 16;
   constexpr int NKH = KP / 32;      // 16-dwell slices per dwell half
   constexpr int NF4 = 4 * KP;       // float4 per 16-point block
   constexpr int NPF = (NF4 + NT - 1) / NT;
 
   __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
-  __shared__ double sX[2][4][4][64];  // partial doses [half][group][r][lane]
-  __shared__ float sPhi[4][4][64];     // phi of the last block [group][r][lane]
-  __shared__ double sF[4][64];         // F partial of the half-1 waves [group][lane]
-  __shared__ float sW[kPT * kGmax];
-  __shared__ int sPlan[kPT];
+  __shared__ double sX[2][NG][4][64];  // partial doses [half][group][r][lane]
+  __shared__ float sPhi[NG][4][64];     // phi of the last block [group][r][lane]
+  __shared__ double sF[NG][64];         // F partial of the half-1 waves [group][lane]
+  __shared__ float sW[NCOL * kGmax];
+  __shared__ int sPlan[NCOL];
   __shared__ int sScan[NT / 64];
   __shared__ double sP64[kGmax + 1][4];
   __shared__ int sG[2][kBM];
@@ -368,11 +375,11 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int n = lane & 15;
-  const int grp = wave & 3;   // plan group: columns 16 grp .. 16 grp + 15
-  const int half = wave >> 2; // dwell half: slices half * NKH .. half * NKH + NKH - 1
+  const int grp = wave % NG;   // plan group: columns 16 grp .. 16 grp + 15
+  const int half = wave / NG;  // dwell half: slices half * NKH .. half * NKH + NKH - 1
 
   int s, S, stride, j0;
-  if (!tile_setup<NT>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
 #pragma unroll
   for (int j = 0; j <= kGmax; ++j)
     if (tid == j) {
@@ -428,7 +435,7 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   }
 
   for (int i = tid; i < kBM * KS; i += NT) sD[1][i] = 0.f;
-  for (int i = tid; i < 4 * 4 * 64; i += NT) (&sPhi[0][0][0])[i] = 0.f;
+  for (int i = tid; i < NG * 4 * 64; i += NT) (&sPhi[0][0][0])[i] = 0.f;
   if (b_begin < b_end) GMCO_PF64(b_begin);
 #pragma unroll 1
   for (int b = b_begin; b <= b_end; ++b) {
@@ -643,7 +650,7 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
     for (int j = 0; j <= kGmax; ++j) sP[j] = a.gt.prm[j];
   }
   int s, S, stride, j0;  // (tile_setup ends with a barrier)
-  if (!tile_setup<NT, TPW>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
+  if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
 
   // B operands of the dose product, t = x^2 at dwells 32 k + 8 q + e, for
   // the plans of columns 16 (NH wave + h) + n (an empty column evaluates t = 0
@@ -929,15 +936,15 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32_grouped(const EvalArgs* __r
   eval_f32<KP, MODE>(args[c], blockIdx.x - start[c]);
 }
 
-template <int KP>
-__global__ __launch_bounds__(512, 1) void k_eval_acc64(EvalArgs a) {
-  eval_acc64<KP>(a, blockIdx.x);
+template <int KP, int NG>
+__global__ __launch_bounds__(128 * NG, 4 / NG) void k_eval_acc64(EvalArgs a) {
+  eval_acc64<KP, NG>(a, blockIdx.x);
 }
-template <int KP>
-__global__ __launch_bounds__(512, 1) void k_eval_acc64_grouped(const EvalArgs* __restrict__ args,
-                                                               const int* __restrict__ start, int n) {
+template <int KP, int NG>
+__global__ __launch_bounds__(128 * NG, 4 / NG) void k_eval_acc64_grouped(const EvalArgs* __restrict__ args,
+                                                                         const int* __restrict__ start, int n) {
   const int c = group_case(start, n, blockIdx.x);
-  eval_acc64<KP>(args[c], blockIdx.x - start[c]);
+  eval_acc64<KP, NG>(args[c], blockIdx.x - start[c]);
 }
 
 template <int KP, int SHAPE>
@@ -991,8 +998,10 @@ template <int KP>
 hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   if (a.grid < 1) return hipErrorInvalidValue;
   const dim3 grid(a.grid), block(256);
-  if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_acc64<KP>), grid, dim3(512), 0, st, a);
+  if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 1)
+    hipLaunchKernelGGL((k_eval_acc64<KP, 2>), grid, dim3(256), 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32_ACC64)
+    hipLaunchKernelGGL((k_eval_acc64<KP, 4>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
@@ -1008,8 +1017,10 @@ template <int KP>
 hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int grid, int dtype, int lp_shape,
                              hipStream_t st) {
   if (grid < 1 || n < 1) return hipErrorInvalidValue;
-  if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_acc64_grouped<KP>), dim3(grid), dim3(512), 0, st, args, start, n);
+  if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 1)
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 2>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32_ACC64)
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4>), dim3(grid), dim3(512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_CHUNK64>), dim3(grid), dim3(256), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32)

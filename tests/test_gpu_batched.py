@@ -53,6 +53,38 @@ def test_batched_rounds_match_single_case_runs(per_case):
         announce(f"rounds_per_graph={R}: identical to single-case runs")
 
 
+def test_half_tile_workgroups_match_full_tile_runs():
+    # The FP64-accumulated kernel's 256-thread shape (32 plans per workgroup,
+    # two workgroups per compute unit) computes every plan as the 512-thread
+    # shape does: single-case runs and grouped lockstep rounds, plain or
+    # replayed, equal the full-tile single-case runs bit for bit.
+    from paper_1904_01567_amd import optimize_many
+    announce("half-tile FP64-accumulated workgroups")
+    single = _planners()
+    for pl in single:
+        pl.optimize(max_iter=60, eps=1e-4)
+    ref = [(pl.weights_x(), pl.metrics()["iterations"]) for pl in single]
+
+    def half(pls):
+        for pl in pls:
+            t = pl.tuning()
+            pl.set_tuning(t["split"], lp_shape=1, xcd_map=t["xcd_map"])
+            assert pl.tuning()["lp_shape"] == 1
+        return pls
+
+    alone = half(_planners())
+    for pl, (x, it) in zip(alone, ref):
+        pl.optimize(max_iter=60, eps=1e-4)
+        np.testing.assert_array_equal(pl.weights_x(), x)
+        np.testing.assert_array_equal(pl.metrics()["iterations"], it)
+    for R in (0, 6):
+        batch = half(_planners())
+        optimize_many(batch, max_iter=60, eps=1e-4, rounds_per_graph=R)
+        for pl, (x, it) in zip(batch, ref):
+            np.testing.assert_array_equal(pl.weights_x(), x)
+            np.testing.assert_array_equal(pl.metrics()["iterations"], it)
+
+
 def test_graph_replays_with_early_exit_match_eager():
     # The relative-variation stop rule stops plans at different rounds; each
     # captured round compacts its context's running plans on the device, so
@@ -168,8 +200,9 @@ def test_uneven_batch_meets_oracle_optima():
 @pytest.mark.parametrize("dtype", ["bf16", "f32acc64"])
 def test_launch_shapes_give_identical_results(dtype):
     # Every launch shape the autotuner chooses from (split count, tile-to-XCD
-    # mapping, BF16 workgroup of 8 x 16 or 4 x 32 plans) evaluates the same
-    # per-plan arithmetic in the same order: results equal bit for bit.
+    # mapping, BF16 workgroup of 8 x 16 or 4 x 32 plans, FP64-accumulated
+    # workgroup of 64 or 32 plans) evaluates the same per-plan arithmetic in
+    # the same order: results equal bit for bit.
     announce(f"launch shapes {dtype}")
     c = cases.case_c1()
     W = cases.hidden_weights(200, seed=71)       # four plan tiles
@@ -178,7 +211,7 @@ def test_launch_shapes_give_identical_results(dtype):
         0.5 + cases.uniform_draws((W.shape[0], c.K), seed=72))
     pl = planner(c, W, dtype=dtype)
     F0, g0 = pl.evaluate(x)
-    shapes = [0, 1] if dtype == "bf16" else [0]
+    shapes = [0, 1]
     for shape in shapes:
         for xm in (0, 1):
             for split in (1, 8, 16):
@@ -201,8 +234,11 @@ def test_launch_shapes_give_identical_results(dtype):
     t = pl.tuning()
     announce(f"autotuned {dtype}: {t} ({us:.1f} us)")
     assert t["split"] == best and t["tuned"] == 1
+    from paper_1904_01567_amd import GmcoError
+    if dtype == "f32acc64":
+        with pytest.raises(GmcoError):  # the plain FP32 kernel has one shape
+            pl.set_tuning(8, lp_shape=1, dtype="f32")
     if dtype == "bf16":
-        from paper_1904_01567_amd import GmcoError
         big = planner(cases.make_case(20, 20, (300, 60, 100, 120), seed=400), W[:8], dtype="bf16")
         with pytest.raises(GmcoError):  # Kp = 416 has one shape
             big.set_tuning(4, lp_shape=1)
