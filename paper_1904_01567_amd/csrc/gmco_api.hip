@@ -305,6 +305,7 @@ EvalArgs eval_args(const gmco_ctx* c, const float* x, bool compacted, int dtype)
   a.grid = compacted ? std::max(grid_max, units * (lp ? d.S_tuned_lp : d.S_tuned)) : a.S * units;
   a.lp_shape = eval_shape(d, dtype);
   a.xcd_map = lp ? d.xcd_lp : d.xcd32;
+  a.last16 = d.K > d.Kp - 16 ? 1 : 0;
   a.gt = c->gt;
   return a;
 }

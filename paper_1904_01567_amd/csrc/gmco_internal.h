@@ -115,6 +115,8 @@ struct EvalArgs {
   int grid;               // workgroups launched; those past the round's grid exit
   int lp_shape;           // BF16 / FP8 workgroup shape (lp_threads, lp_halves)
   int xcd_map;            // 1: tiles of one point range on one XCD when the grid allows
+  int last16;             // 0: dwells Kp - 16 .. Kp - 1 are all padding (FP32-operand
+                          // kernels skip that 16-dwell slice: its products are zero)
   GroupTable gt;
 };
 

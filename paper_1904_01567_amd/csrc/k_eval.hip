@@ -256,6 +256,7 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
       double ds[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
+        if (k == NK16 - 1 && !a.last16) continue;  // all-padding slice: zero products
         const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
         // one 16-dwell partial per slice, interleaved with the back-projection
         f4v c0 = mfma_f32(av.x, tf[4 * k + 0], z);
@@ -286,6 +287,7 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
       f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
+        if (k == NK16 - 1 && !a.last16) continue;  // all-padding slice: zero products
         const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
         acc0 = mfma_f32(av.x, tf[4 * k + 0], acc0);
         acc1 = mfma_f32(av.y, tf[4 * k + 1], acc1);
@@ -377,6 +379,9 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   const int n = lane & 15;
   const int grp = wave % NG;   // plan group: columns 16 grp .. 16 grp + 15
   const int half = wave / NG;  // dwell half: slices half * NKH .. half * NKH + NKH - 1
+  // the last slice of the upper half holds only padding dwells when
+  // Kp - K >= 16: its products are zero, so the wave skips it (a scalar branch)
+  const bool skip_last = __builtin_amdgcn_readfirstlane(half) == 1 && !a.last16;
 
   int s, S, stride, j0;
   if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
@@ -461,6 +466,7 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
     d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
 #pragma unroll
     for (int k = 0; k < NKH; ++k) {
+      if (k == NKH - 1 && skip_last) continue;
       const int kg = half * NKH + k;
       const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * kg + 4 * (q ^ swz_row(n))]);
       acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
