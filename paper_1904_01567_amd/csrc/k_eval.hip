@@ -30,6 +30,14 @@ __device__ inline f4v mfma_f32(float a, float b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// True (the same in every lane) when any lane holds a nonzero penalty
+// derivative: the back-projection of a block whose phi is zero for every
+// point and plan of the wave adds only zero products, so it is skipped.
+__device__ inline bool wave_any_nonzero(const float (&phi)[4]) {
+  const bool nz = phi[0] != 0.f || phi[1] != 0.f || phi[2] != 0.f || phi[3] != 0.f;
+  return __builtin_amdgcn_ballot_w64(nz) != 0;
+}
+
 // FP64 matrix op on FP32 operands: the products are exact in FP64 and the
 // dose accumulates without FP32 rounding (same lane layout as the FP32 op).
 __device__ inline d4v mfma_f64(float a, float b, d4v c) {
@@ -213,23 +221,24 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
 #define GMCO_PREFETCH(blk)                                                  \
   {                                                                         \
     const f4v* src_ = Dg + (size_t)(blk) * NF4;                             \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
-      const int idx = tid + 256 * i;                                        \
-      if (NF4 % 256 == 0 || idx < NF4) pf[i] = src_[idx];                   \
+    _Pragma("unroll") for (int i_ = 0; i_ < NPF; ++i_) {                    \
+      const int idx = tid + 256 * i_;                                       \
+      if (NF4 % 256 == 0 || idx < NF4) pf[i_] = src_[idx];                  \
     }                                                                       \
     if (tid < kBM) gpre = a.grp[(blk) * kBM + tid];                         \
   }
 #define GMCO_STAGE(buf)                                                     \
   {                                                                         \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
-      const int idx = tid + 256 * i;                                        \
+    const int buf_ = (buf);                                                 \
+    _Pragma("unroll") for (int i_ = 0; i_ < NPF; ++i_) {                    \
+      const int idx = tid + 256 * i_;                                       \
       if (NF4 % 256 == 0 || idx < NF4) {                                    \
         const int row = idx / (KP / 4);                                     \
         const int c4 = idx - row * (KP / 4);                                \
-        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * c4]) = pf[i];     \
+        *reinterpret_cast<f4v*>(&sD[buf_][row * KS + 4 * c4]) = pf[i_];     \
       }                                                                     \
     }                                                                       \
-    if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
+    if (tid < kBM) sG[buf_][tid] = gpre;                                    \
   }
 
   float phi_prev[4] = {0.f, 0.f, 0.f, 0.f};
@@ -285,6 +294,10 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
       }
     } else {
       f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+      // (Skipping the back-projection of a block whose phi is zero, as the
+      // FP64-accumulating kernel does, measured slower here: with one wave
+      // per SIMD the back-projection's independent ops fill the gaps of the
+      // two dose chains, and the split loop loses that.)
 #pragma unroll
       for (int k = 0; k < NK16; ++k) {
         if (k == NK16 - 1 && !a.last16) continue;  // all-padding slice: zero products
@@ -420,23 +433,24 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 #define GMCO_PF64(blk)                                                      \
   {                                                                         \
     const f4v* src_ = Dg + (size_t)(blk) * NF4;                             \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
-      const int idx = tid + NT * i;                                         \
-      if (NF4 % NT == 0 || idx < NF4) pf[i] = src_[idx];                    \
+    _Pragma("unroll") for (int i_ = 0; i_ < NPF; ++i_) {                    \
+      const int idx = tid + NT * i_;                                        \
+      if (NF4 % NT == 0 || idx < NF4) pf[i_] = src_[idx];                   \
     }                                                                       \
     if (tid < kBM) gpre = a.grp[(blk) * kBM + tid];                         \
   }
 #define GMCO_ST64(buf)                                                      \
   {                                                                         \
-    _Pragma("unroll") for (int i = 0; i < NPF; ++i) {                       \
-      const int idx = tid + NT * i;                                         \
+    const int buf_ = (buf);                                                 \
+    _Pragma("unroll") for (int i_ = 0; i_ < NPF; ++i_) {                    \
+      const int idx = tid + NT * i_;                                        \
       if (NF4 % NT == 0 || idx < NF4) {                                     \
         const int row = idx / (KP / 4);                                     \
         const int c4 = idx - row * (KP / 4);                                \
-        *reinterpret_cast<f4v*>(&sD[(buf)][row * KS + 4 * (c4 ^ swz_row(row))]) = pf[i]; \
+        *reinterpret_cast<f4v*>(&sD[buf_][row * KS + 4 * (c4 ^ swz_row(row))]) = pf[i_]; \
       }                                                                     \
     }                                                                       \
-    if (tid < kBM) sG[(buf)][tid] = gpre;                                   \
+    if (tid < kBM) sG[buf_][tid] = gpre;                                    \
   }
 
   for (int i = tid; i < kBM * KS; i += NT) sD[1][i] = 0.f;
@@ -464,6 +478,8 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) phi_prev[r] = sPhi[grp][r][lane];
     d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    // the dose product of block b, then the back-projection of block b-1,
+    // skipped when phi is zero for all 16 points and 16 plans of the wave
 #pragma unroll
     for (int k = 0; k < NKH; ++k) {
       if (k == NKH - 1 && skip_last) continue;
@@ -473,10 +489,17 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
       acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
       acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
       acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
+    }
+    if (wave_any_nonzero(phi_prev)) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * kg + (n ^ (swz_row(q + 4 * r) << 2))],
-                           phi_prev[r], gacc[k]);
+      for (int k = 0; k < NKH; ++k) {
+        if (k == NKH - 1 && skip_last) continue;
+        const int kg = half * NKH + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * kg + (n ^ (swz_row(q + 4 * r) << 2))],
+                             phi_prev[r], gacc[k]);
+      }
     }
     // partial dose of points q + 4 r (the FP64 op's rows) for plan n
 #pragma unroll
