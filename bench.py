@@ -570,9 +570,10 @@ def main(argv=None) -> int:
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
     ap.add_argument("--history", type=int, default=10, help="L-BFGS pairs m")
-    ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1],
+    ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1, 2],
                     help="workgroup shape of the FP64-accumulated kernel (0: 512 threads per "
-                         "64 plans, 1: 256 threads per 32 plans); default: the library's")
+                         "64 plans, 1: 256 threads per 32 plans, 2: 1,024 threads per 64 plans "
+                         "in dwell quarters); default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-plans", type=int, default=16,
                     help="plans of the oracle's host timing, spread over the batch")

@@ -308,8 +308,11 @@ typedef struct {
   int tuned;     /* 1: split set by the autotuner or the caller */
   int lp_shape;  /* workgroup shape.  BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32
                     (Kp <= 384).  FP32 operands with FP64-accumulated dose: 0 = 512
-                    threads per 64-plan tile, 1 = 256 threads per 32 plans (two
-                    workgroups per compute unit).  Plain FP32: 0 */
+                    threads per 64-plan tile (dwell halves), 1 = 256 threads per 32
+                    plans (two workgroups per compute unit), 2 = 1,024 threads per
+                    64-plan tile (dwell quarters, four waves per SIMD; Kp a
+                    multiple of 64; the dose partials are added in another
+                    order, an FP64 rounding difference).  Plain FP32: 0 */
   int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
 } gmco_tuning;
 

@@ -28,6 +28,10 @@ __host__ __device__ constexpr int lp_threads(int Kp, int shape = 0) {
 __host__ __device__ constexpr int lp_halves(int Kp, int shape = 0) {
   return (Kp == 416 || (Kp <= 384 && shape == 1)) ? 2 : 1;
 }
+// FP64-accumulated evaluation, workgroup shape 2: dwell quarters (1,024
+// threads, four waves per SIMD), for padded dwell counts that are multiples
+// of 64.
+__host__ __device__ constexpr bool acc_quarters_ok(int Kp) { return Kp % 64 == 0; }
 __host__ __device__ constexpr int lp_tiles(int Kp) { return lp_threads(Kp) / 64 * 16 * lp_halves(Kp) / kPT; }
 constexpr int kKAlign = 32;
 constexpr int kMAlign = 32;  // points: a multiple of every kernel's block

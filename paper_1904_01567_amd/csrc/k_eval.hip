@@ -361,24 +361,32 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
 // q = 0, 1, and the swizzle keeps the dose product's float4 reads of rows
 // 0..15 conflict-free.
 // ---------------------------------------------------------------------------
-// NG plan groups of 16 per workgroup: NG = 4 (512 threads, one workgroup of
-// 64 plans per CU) or NG = 2 (256 threads, 32 plans, half a tile; two
-// workgroups per CU whose barriers and eq. 1 phases are independent, so one
-// can run its matrix ops while the other waits).  Per plan the arithmetic
-// and its order are the same in both.
-template <int KP, int NG>
+// NG plan groups of 16 per workgroup and NH dwell parts per group:
+//   NG = 4, NH = 2: 512 threads, one workgroup of 64 plans per CU;
+//   NG = 2, NH = 2: 256 threads, 32 plans (half a tile), two workgroups per
+//                   CU whose barriers and eq. 1 phases are independent;
+//   NG = 4, NH = 4: 1,024 threads, 64 plans, four waves per SIMD (dwell
+//                   quarters, Kp a multiple of 64): a wave holds a quarter of
+//                   the registers, and while some waves wait (LDS, barrier,
+//                   epilogue) the others keep the FP64 matrix pipe fed.
+// Per plan the arithmetic and its order are the same for a given NH; the
+// NH = 4 shape adds the dose partials of four quarters instead of two
+// halves (an FP64 rounding difference).
+template <int KP, int NG, int NH = 2>
 __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
-  constexpr int NT = 128 * NG;
+  static_assert((NH == 2 || NH == 4) && KP % (16 * NH) == 0, "dwell parts of whole 16-dwell slices");
+  constexpr int NT = 64 * NG * NH;
   constexpr int NCOL = 16 * NG;
   constexpr int KS = KP + 16;
-  constexpr int NKH = KP / 32;      // 16-dwell slices per dwell half
-  constexpr int NF4 = 4 * KP;       // float4 per 16-point block
+  constexpr int NKH = KP / (16 * NH);  // 16-dwell slices per dwell part
+  constexpr int RPW = 4 / NH;          // epilogue rows per wave
+  constexpr int NF4 = 4 * KP;          // float4 per 16-point block
   constexpr int NPF = (NF4 + NT - 1) / NT;
 
   __shared__ __attribute__((aligned(16))) float sD[2][kBM * KS];
-  __shared__ double sX[2][NG][4][64];  // partial doses [half][group][r][lane]
-  __shared__ float sPhi[NG][4][64];     // phi of the last block [group][r][lane]
-  __shared__ double sF[NG][64];         // F partial of the half-1 waves [group][lane]
+  __shared__ double sX[NH][NG][4][64];  // partial doses [part][group][r][lane]
+  __shared__ float sPhi[NG][4][64];      // phi of the last block [group][r][lane]
+  __shared__ double sF[NH - 1][NG][64];  // F partials of the waves of parts 1.. [part-1][group][lane]
   __shared__ float sW[NCOL * kGmax];
   __shared__ int sPlan[NCOL];
   __shared__ int sScan[NT / 64];
@@ -391,10 +399,10 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   const int q = lane >> 4;
   const int n = lane & 15;
   const int grp = wave % NG;   // plan group: columns 16 grp .. 16 grp + 15
-  const int half = wave / NG;  // dwell half: slices half * NKH .. half * NKH + NKH - 1
-  // the last slice of the upper half holds only padding dwells when
+  const int half = wave / NG;  // dwell part: slices half * NKH .. half * NKH + NKH - 1
+  // the last slice of the last part holds only padding dwells when
   // Kp - K >= 16: its products are zero, so the wave skips it (a scalar branch)
-  const bool skip_last = __builtin_amdgcn_readfirstlane(half) == 1 && !a.last16;
+  const bool skip_last = __builtin_amdgcn_readfirstlane(half) == NH - 1 && !a.last16;
 
   int s, S, stride, j0;
   if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
@@ -408,9 +416,9 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   const int col = grp * 16 + n;
   const int plan = sPlan[col];
   const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
-  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP + half * (KP / 2);
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP + half * (KP / NH);
   // t = x^2 of plan n at dwells 16 k + 4 q + j of this wave's half (slice k)
-  float tf[KP / 8];
+  float tf[4 * NKH];
 #pragma unroll
   for (int k = 0; k < NKH; ++k) {
     const float4 xv = *reinterpret_cast<const float4*>(xrow + 16 * k + 4 * q);
@@ -478,6 +486,13 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) phi_prev[r] = sPhi[grp][r][lane];
     d4v acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    if constexpr (NH == 4) {
+      // t stays FP32 in registers (a quarter-wave has 128 of them): mark it
+      // as changed each block so that its FP64 conversion is redone per use
+      // rather than kept live for the whole loop
+#pragma unroll
+      for (int i = 0; i < 4 * NKH; ++i) asm("" : "+v"(tf[i]));
+    }
     // the dose product of block b, then the back-projection of block b-1,
     // skipped when phi is zero for all 16 points and 16 plans of the wave
 #pragma unroll
@@ -485,10 +500,18 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
       if (k == NKH - 1 && skip_last) continue;
       const int kg = half * NKH + k;
       const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * kg + 4 * (q ^ swz_row(n))]);
-      acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
-      acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
-      acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
-      acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
+      if constexpr (NH == 4) {
+        // two accumulator chains (four waves per SIMD interleave them)
+        acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
+        acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
+        acc0 = mfma_f64(av.z, tf[4 * k + 2], acc0);
+        acc1 = mfma_f64(av.w, tf[4 * k + 3], acc1);
+      } else {
+        acc0 = mfma_f64(av.x, tf[4 * k + 0], acc0);
+        acc1 = mfma_f64(av.y, tf[4 * k + 1], acc1);
+        acc2 = mfma_f64(av.z, tf[4 * k + 2], acc2);
+        acc3 = mfma_f64(av.w, tf[4 * k + 3], acc3);
+      }
     }
     if (wave_any_nonzero(phi_prev)) {
 #pragma unroll
@@ -505,14 +528,16 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) sX[half][grp][r][lane] = (acc0[r] + acc1[r]) + (acc2[r] + acc3[r]);
     __syncthreads();
-    // eq. 1 on the summed dose: each wave of the group takes two of the four
-    // rows (points q + 4r) and shares phi through LDS; the next iteration's
-    // first barrier orders these writes before their reads
+    // eq. 1 on the summed dose: each wave of the group takes 4 / NH of the
+    // four rows (points q + 4r) and shares phi through LDS; the next
+    // iteration's first barrier orders these writes before their reads
     if (have_cur) {
 #pragma unroll
-      for (int rr = 0; rr < 2; ++rr) {
-        const int r = 2 * half + rr;
-        const double d = sX[0][grp][r][lane] + sX[1][grp][r][lane];
+      for (int rr = 0; rr < RPW; ++rr) {
+        const int r = RPW * half + rr;
+        double d = sX[0][grp][r][lane] + sX[1][grp][r][lane];
+#pragma unroll
+        for (int h = 2; h < NH; ++h) d += sX[h][grp][r][lane];
         const int gi = sG[cur][q + 4 * r];
         const float w = (gi < kGmax) ? sW[col * kGmax + gi] : 0.f;
         // without branches: at most one of the two deviations is nonzero
@@ -527,18 +552,19 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 #undef GMCO_PF64
 #undef GMCO_ST64
 
-  // ---- split partials: each wave its dwell half; F from one wave per group ----
-  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP + half * (KP / 2);
+  // ---- split partials: each wave its dwell part; F from one wave per group ----
+  float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP + half * (KP / NH);
 #pragma unroll
   for (int k = 0; k < NKH; ++k) {
     *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
         make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
   }
-  // F partial: rows 0-1 (half 0) + rows 2-3 (half 1), then over q
-  if (half == 1) sF[grp][lane] = facc;
+  // F partial: the rows of part 0, then those of parts 1.. in order, then over q
+  if (half > 0) sF[half - 1][grp][lane] = facc;
   __syncthreads();
   if (half == 0) {
-    facc += sF[grp][lane];
+#pragma unroll
+    for (int h = 1; h < NH; ++h) facc += sF[h - 1][grp][lane];
     facc += __shfl_xor(facc, 16);
     facc += __shfl_xor(facc, 32);
     if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
@@ -965,15 +991,15 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32_grouped(const EvalArgs* __r
   eval_f32<KP, MODE>(args[c], blockIdx.x - start[c]);
 }
 
-template <int KP, int NG>
-__global__ __launch_bounds__(128 * NG, 4 / NG) void k_eval_acc64(EvalArgs a) {
-  eval_acc64<KP, NG>(a, blockIdx.x);
+template <int KP, int NG, int NH>
+__global__ __launch_bounds__(64 * NG * NH, (NG * NH == 4) ? 2 : 1) void k_eval_acc64(EvalArgs a) {
+  eval_acc64<KP, NG, NH>(a, blockIdx.x);
 }
-template <int KP, int NG>
-__global__ __launch_bounds__(128 * NG, 4 / NG) void k_eval_acc64_grouped(const EvalArgs* __restrict__ args,
-                                                                         const int* __restrict__ start, int n) {
+template <int KP, int NG, int NH>
+__global__ __launch_bounds__(64 * NG * NH, (NG * NH == 4) ? 2 : 1) void k_eval_acc64_grouped(
+    const EvalArgs* __restrict__ args, const int* __restrict__ start, int n) {
   const int c = group_case(start, n, blockIdx.x);
-  eval_acc64<KP, NG>(args[c], blockIdx.x - start[c]);
+  eval_acc64<KP, NG, NH>(args[c], blockIdx.x - start[c]);
 }
 
 template <int KP, int SHAPE>
@@ -1028,9 +1054,12 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   if (a.grid < 1) return hipErrorInvalidValue;
   const dim3 grid(a.grid), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 1)
-    hipLaunchKernelGGL((k_eval_acc64<KP, 2>), grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_eval_acc64<KP, 2, 2>), grid, dim3(256), 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 2 && acc_quarters_ok(KP))
+    hipLaunchKernelGGL((k_eval_acc64<KP, 4, (KP % 64 == 0 ? 4 : 2)>), grid, dim3(KP % 64 == 0 ? 1024 : 512), 0, st,
+                       a);
   else if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_acc64<KP, 4>), grid, dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_eval_acc64<KP, 4, 2>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
@@ -1047,9 +1076,12 @@ hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int 
                              hipStream_t st) {
   if (grid < 1 || n < 1) return hipErrorInvalidValue;
   if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 1)
-    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 2>), dim3(grid), dim3(256), 0, st, args, start, n);
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 2, 2>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 2 && acc_quarters_ok(KP))
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4, (KP % 64 == 0 ? 4 : 2)>), dim3(grid),
+                       dim3(KP % 64 == 0 ? 1024 : 512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32_ACC64)
-    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4>), dim3(grid), dim3(512), 0, st, args, start, n);
+    hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4, 2>), dim3(grid), dim3(512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_CHUNK64>), dim3(grid), dim3(256), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32)

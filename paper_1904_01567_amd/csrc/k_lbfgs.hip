@@ -379,6 +379,19 @@ __device__ inline void reduce_g(const float* __restrict__ Gpart, const RoundTabl
   const float4* src = reinterpret_cast<const float4*>(Gpart + (size_t)j * Kp) + c;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   int s = 0;
+  // up to 16 loads in flight per thread, summed in split order
+  for (; s + 16 <= r.S; s += 16) {
+    float4 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = src[(s + u) * stride / 4];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      acc.x += v[u].x;
+      acc.y += v[u].y;
+      acc.z += v[u].z;
+      acc.w += v[u].w;
+    }
+  }
   for (; s + 8 <= r.S; s += 8) {
     float4 v[8];
 #pragma unroll

@@ -85,6 +85,52 @@ def test_half_tile_workgroups_match_full_tile_runs():
             np.testing.assert_array_equal(pl.metrics()["iterations"], it)
 
 
+def test_dwell_quarter_workgroups_follow_the_half_shape():
+    # Shape 2 of the FP64-accumulated kernel (1,024 threads, dwell quarters,
+    # four waves per SIMD; Kp a multiple of 64) adds four dose partials where
+    # shape 0 adds two: the same FP64 sums in another order.  Its evaluation
+    # equals shape 0's to FP64 rounding, its runs follow the oracle as shape
+    # 0's do, grouped rounds equal single-case runs bit for bit, and it is
+    # refused where Kp is not a multiple of 64.
+    from paper_1904_01567_amd import GmcoError, optimize_many
+    announce("dwell-quarter FP64-accumulated workgroups")
+    mk = lambda i: cases.make_case(12, 16, (600, 120, 240, 240), seed=81 + i, jitter=0.2)  # K = 192
+    c = mk(0)
+    D = O.dose_rate_matrix(c.dwell_xyz, c.pt_xyz)
+    W = cases.hidden_weights(100, seed=83)
+    x = np.sqrt(O.uniform_start_time(D, c.group, 15.0)) * (0.5 + cases.uniform_draws((W.shape[0], c.K), seed=84))
+    pl = planner(c, W, dtype="f32acc64")
+    t = pl.tuning()
+    Fa, ga = pl.evaluate(x)
+    pl.set_tuning(t["split"], lp_shape=2, xcd_map=t["xcd_map"])
+    assert pl.tuning()["lp_shape"] == 2
+    Fq, gq = pl.evaluate(x)
+    np.testing.assert_allclose(Fq, Fa, rtol=1e-13)
+    assert np.abs(gq - ga).max() <= 1e-6 * np.abs(ga).max()
+    Fr, gr = O.objective_and_gradient_x(D, x, c.group, PARAMS, W)
+    assert np.max(np.abs(Fq - Fr) / Fr) <= 2e-5
+    # grouped rounds (two cases of Kp = 192 in one launch, plain and replayed)
+    # equal single-case runs of the same shape bit for bit
+    def quarter(pls):
+        for q in pls:
+            tq = q.tuning()
+            q.set_tuning(tq["split"], lp_shape=2, xcd_map=tq["xcd_map"])
+        return pls
+    mk_pls = lambda: quarter([planner(mk(i), cases.hidden_weights(70 + 30 * i, seed=85 + i), dtype="f32acc64")
+                              for i in range(2)])
+    single = mk_pls()
+    for q in single:
+        q.optimize(max_iter=40, eps=1e-4)
+    ref = [q.weights_x() for q in single]
+    for R in (0, 6):
+        batch = mk_pls()
+        optimize_many(batch, max_iter=40, eps=1e-4, rounds_per_graph=R)
+        for q, xr in zip(batch, ref):
+            np.testing.assert_array_equal(q.weights_x(), xr)
+    with pytest.raises(GmcoError):  # Kp = 160
+        planner(cases.case_c1(), cases.weights_c1(), dtype="f32acc64").set_tuning(4, lp_shape=2)
+
+
 def test_graph_replays_with_early_exit_match_eager():
     # The relative-variation stop rule stops plans at different rounds; each
     # captured round compacts its context's running plans on the device, so
