@@ -466,7 +466,7 @@ def batched(args) -> int:
     stages = args.stages
     run_eps = DEFAULT_EPS if args.eps is None else args.eps
     side = torch.cuda.Stream()
-    planners, Ws, shapes, splits = [], [], [], []
+    planners, Ws, shapes, splits, wg_shapes = [], [], [], [], []
     t0 = time.perf_counter()
     with torch.cuda.stream(side):
         for i in range(args.batched):
@@ -475,7 +475,9 @@ def batched(args) -> int:
             pl = Planner(dtype=stages[0][0], max_plans=args.plans, history=args.history)
             pl.load(c, class_solution.VOLUME)
             pl.set_weights(W)
-            splits.append([pl.autotune(dtype=d, reps=3)[0] for d in sorted({d for d, _ in stages})])
+            fams = sorted({d for d, _ in stages})
+            splits.append([pl.autotune(dtype=d, reps=3)[0] for d in fams])
+            wg_shapes.append([pl.tuning(d)["lp_shape"] for d in fams])
             planners.append(pl)
             Ws.append(W)
             shapes.append((c.K, c.M))
@@ -550,6 +552,7 @@ def batched(args) -> int:
                             "note": "evaluation FLOPs of the last stage / its whole device time "
                                     "(reductions and updates included)"},
         "autotuned_splits": splits,
+        "autotuned_workgroup_shapes": wg_shapes,
         "setup_s": t_setup,
     }
     print(json.dumps(out), flush=True)

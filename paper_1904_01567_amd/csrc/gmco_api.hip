@@ -424,15 +424,16 @@ int gmco_create(gmco_ctx** out, const gmco_opts* o) {
 
 int gmco_destroy(gmco_ctx* c) {
   if (!c) return GMCO_OK;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
-  if (c->ws_owned && c->ws) hipFree(c->ws);
-  if (c->host_count) hipHostFree(c->host_count);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
-  if (c->gev) hipEventDestroy(c->gev);
-  if (c->gstream) hipStreamDestroy(c->gstream);
+  // best-effort teardown: errors here have no caller to go to
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+  if (c->host_count) (void)hipHostFree(c->host_count);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->gev) (void)hipEventDestroy(c->gev);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   delete c;
   return GMCO_OK;
 }
@@ -513,14 +514,14 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   // arena: bound workspace, else a library allocation (reused when big enough)
   if (c->bound) {
     if (c->bound_bytes < L.total) return fail(c, GMCO_ENOMEM, "bound workspace smaller than gmco_workspace_bytes");
-    if (c->ws_owned && c->ws) hipFree(c->ws);
+    if (c->ws_owned && c->ws) (void)hipFree(c->ws);  // (the old arena; nothing to report)
     c->ws = c->bound;
     c->ws_bytes = c->bound_bytes;
     c->ws_owned = false;
   } else if (!c->ws_owned || c->ws_bytes < L.total) {
     if (c->ws_owned && c->ws) {
-      hipStreamSynchronize(c->stream);
-      hipFree(c->ws);
+      GMCO_HIP(c, hipStreamSynchronize(c->stream));
+      GMCO_HIP(c, hipFree(c->ws));
     }
     c->ws = nullptr;
     c->ws_owned = false;
@@ -743,7 +744,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
   for (auto& e : ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       for (auto& f : ev)
-        if (f) hipEventDestroy(f);
+        if (f) (void)hipEventDestroy(f);
       return fail(c, GMCO_EHIP, "hipEventCreate failed");
     }
   }
@@ -751,7 +752,7 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
     std::vector<hipEvent_t>& v;
     ~EventGuard() {
       for (auto& e : v)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     }
   } guard{ev};
   bev[0] = ev[ev.size() - 2];
@@ -887,7 +888,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
   struct TabGuard {
     void*& p;
     ~TabGuard() {
-      if (p) hipFree(p);
+      if (p) (void)hipFree(p);
     }
   } tab_guard{dtab};
   EvalArgs* d_eargs = nullptr;
@@ -979,7 +980,7 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     hipEvent_t* e;
     ~BevGuard() {
       for (int k = 0; k < 2; ++k)
-        if (e[k]) hipEventDestroy(e[k]);
+        if (e[k]) (void)hipEventDestroy(e[k]);
     }
   } bev_guard{bev};
   for (int k = 0; k < 2; ++k)
@@ -1042,16 +1043,16 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     for (int k = 0; k < R && rc == GMCO_OK; ++k) rc = issue_round(k);
     hipError_t ee = hipStreamEndCapture(st, &graph);
     if (rc) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return rc;
     }
     if (ee != hipSuccess) return hip_fail(c0, ee, "hipStreamEndCapture");
     ee = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ee != hipSuccess) return hip_fail(c0, ee, "hipGraphInstantiate");
     struct ExecGuard {
       hipGraphExec_t e;
-      ~ExecGuard() { hipGraphExecDestroy(e); }
+      ~ExecGuard() { (void)hipGraphExecDestroy(e); }
     } eg{exec};
     while (true) {
       GMCO_HIP(c0, hipGraphLaunch(exec, st));
@@ -1237,6 +1238,8 @@ int gmco_set_split(gmco_ctx* c, int split) {
   return GMCO_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // Checkpoint blob: this header, then the first P rows of each plan-major
 // array in the order of state_arrays().
@@ -1270,6 +1273,8 @@ size_t state_size(const gmco_ctx* c, int P) {
   return n;
 }
 }  // namespace
+
+extern "C" {
 
 int gmco_state_bytes(const gmco_ctx* c, size_t* bytes) {
   if (!c || !bytes) return GMCO_EINVAL;
@@ -1379,6 +1384,8 @@ int gmco_get_weights_x(gmco_ctx* c, double* x) {
   return GMCO_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // FP64 metrics at the current t: doses of the optimisation points give F and
 // the individual objectives (and the DVH metrics when the case has no DVH
@@ -1420,6 +1427,8 @@ int compute_metrics(gmco_ctx* c) {
   return GMCO_OK;
 }
 }  // namespace
+
+extern "C" {
 
 int gmco_select_plan(gmco_ctx* c, const gmco_select_opts* opts, int* best, int* plan_class, int* nondominated,
                      double* nondominated_fraction) {

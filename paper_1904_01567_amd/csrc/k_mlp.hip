@@ -155,6 +155,7 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 __global__ void k_gather_rows(const float* __restrict__ src, const int* __restrict__ idx, int B, int N,
                               float* __restrict__ dst) {
   const int i = blockIdx.x;
+  if (i >= B) return;
   const size_t s = (size_t)idx[i];
   for (int j = threadIdx.x; j < N; j += blockDim.x) dst[(size_t)i * N + j] = src[s * N + j];
 }
@@ -166,6 +167,7 @@ __global__ void k_features(const double* __restrict__ dwell, const double* __res
                            const int* __restrict__ perm, const int* __restrict__ goff,
                            const int* __restrict__ gcnt, int K, unsigned* __restrict__ hist) {
   const int l = blockIdx.x, j = blockIdx.y;
+  if (l >= K) return;  // (whole workgroup)
   __shared__ double red[256];
   double best = 1e300;
   const double qx = dwell[3 * l], qy = dwell[3 * l + 1], qz = dwell[3 * l + 2];
