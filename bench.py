@@ -467,6 +467,10 @@ def batched(args) -> int:
     run_eps = DEFAULT_EPS if args.eps is None else args.eps
     side = torch.cuda.Stream()
     planners, Ws, shapes, splits, wg_shapes = [], [], [], [], []
+    tcache = None
+    if args.tuning_cache:
+        from paper_1904_01567_amd.tuning import TuningCache
+        tcache = TuningCache(args.tuning_cache)
     t0 = time.perf_counter()
     with torch.cuda.stream(side):
         for i in range(args.batched):
@@ -476,13 +480,18 @@ def batched(args) -> int:
             pl.load(c, class_solution.VOLUME)
             pl.set_weights(W)
             fams = sorted({d for d, _ in stages})
-            splits.append([pl.autotune(dtype=d, reps=3)[0] for d in fams])
+            if tcache is None:
+                splits.append([pl.autotune(dtype=d, reps=3)[0] for d in fams])
+            else:
+                splits.append([tcache.tune(pl, d, reps=3)["split"] for d in fams])
             wg_shapes.append([pl.tuning(d)["lp_shape"] for d in fams])
             planners.append(pl)
             Ws.append(W)
             shapes.append((c.K, c.M))
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    if tcache is not None:
+        tcache.save()
     print(f"# {args.batched} cases loaded and tuned in {t_setup:.1f} s", file=sys.stderr, flush=True)
 
     def step():
@@ -553,6 +562,8 @@ def batched(args) -> int:
                                     "(reductions and updates included)"},
         "autotuned_splits": splits,
         "autotuned_workgroup_shapes": wg_shapes,
+        "tuning_cache": None if tcache is None else {"file": args.tuning_cache, "hits": tcache.hits,
+                                                     "misses": tcache.misses},
         "setup_s": t_setup,
     }
     print(json.dumps(out), flush=True)
@@ -587,6 +598,9 @@ def main(argv=None) -> int:
                          "points, semi-axes +-20 %%) of --plans plans each in lockstep rounds "
                          "replayed from a captured HIP graph, splits autotuned per shape")
     ap.add_argument("--rounds-per-graph", type=int, default=16)
+    ap.add_argument("--tuning-cache", type=str, default=None,
+                    help="--batched: reuse autotuned launch shapes per (kernel family, padded dwells, "
+                         "point bucket, plans) from this JSON file, and add new ones to it")
     ap.add_argument("--eps-sweep", type=str, default=None,
                     help="comma-separated stop thresholds: time, iterations and non-dominated "
                          "fraction at each (speed-up relative to the first)")

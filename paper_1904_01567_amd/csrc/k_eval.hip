@@ -593,9 +593,10 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
 // penalty derivative of points {4q..4q+3} and {16+4q..16+4q+3} of its plan,
 // exactly the 8 contraction slots it supplies to the back-projection, whose
 // A operand (D transposed) is read in that point order from a dwell-major
-// tile.  The BF16 kernel writes that tile itself from the row-major block it
-// stages (two points per 32-bit word), so D is read from memory once; the
-// FP8 kernel loads it from the BF16 transposed copy.
+// tile.  Both kernels stage that tile from the BF16 transposed copy of D,
+// which stores every 32-point block in this point order.  (Building it in
+// the kernel from the row-major block with byte permutes, which reads D from
+// memory once, measured 58.5-58.8 us per launch against 55.9-58.7 us.)
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
@@ -628,14 +629,6 @@ __device__ inline __bf16 penalty_lp(float d, float4 pw, float& f) {
   const float phi = pw.x * lo + pw.w * hi;
   f = fmaf(phi, lo + hi, f);
   return (__bf16)phi;
-}
-
-// Position of point r of a 32-point block in a dwell row of the transposed
-// tile: the 8 contraction slots lane quad q supplies to the back-projection
-// (the dose product's rows 4q .. 4q+3 and 16+4q .. 16+4q+3) are positions
-// 8q .. 8q+7, so each lane reads its operand as one 16-byte access.
-__host__ __device__ constexpr int tpos(int r) {
-  return r < 16 ? 8 * (r >> 2) + (r & 3) : 8 * ((r - 16) >> 2) + 4 + ((r - 16) & 3);
 }
 
 template <bool FP8>
@@ -673,17 +666,15 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   constexpr int NCOL = NW * 16 * NH;
   constexpr int TPW = NCOL / kPT;
   static_assert(TPW == lp_tiles(KP) && TPW * kPT == NCOL, "workgroup of whole plan tiles");
-  // BF16 staging: (row pair, 8-dwell chunk) tasks, row pair fastest
-  constexpr int NC8 = KP / 8;
-  constexpr int NTASK = (BMP / 2) * NC8;
-  constexpr int NPT = FP8 ? 1 : (NTASK + NT - 1) / NT;
+  constexpr int NC8 = KP / 8;  // 16-byte chunks of a BF16 row
   // FP8 staging: 16-byte chunks of the FP8 tile and of the BF16 transposed tile
   constexpr int NCH8 = BMP * KP / 16;
   constexpr int NCH = BMP * KP / 8;
   constexpr int NPF8 = FP8 ? (NCH8 + NT - 1) / NT : 1;
-  constexpr int NPF = FP8 ? (NCH + NT - 1) / NT : 1;
-  static_assert(NC8 % 4 == 0, "a wavefront's staging tasks span whole chunk groups");
+  constexpr int NPF = (NCH + NT - 1) / NT;
   constexpr int SDB = BMP * DS * (FP8 ? 1 : 2);  // bytes of one D tile
+  constexpr int NCHB = BMP * KP / 8;  // 16-byte chunks of the BF16 D tile
+  constexpr int NPFB = FP8 ? 1 : (NCHB + NT - 1) / NT;
 
   // two buffers: block b is read from one while block b + 1 is staged in the other
   __shared__ __attribute__((aligned(16))) unsigned char sD[2][SDB];
@@ -775,32 +766,26 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
   const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
 
-  u4v p0[NPT], p1[NPT];    // BF16: rows 2 rp and 2 rp + 1 of chunk c8
-  u4v pd[NPF8], pt[NPF];   // FP8: tile chunks, transposed-tile chunks
+  u4v pd[NPF8], pb[NPFB];  // FP8 / BF16 D tile chunks
+  u4v pt[NPF];             // transposed-tile chunks
   int gpre = 0;
   auto prefetch = [&](int blk) {
     // threads past the last chunk load the last one again (every register
     // is defined on every path) and do not store it
-    if constexpr (!FP8) {
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int c = min(tid + NT * i, NTASK - 1);
-        const int rp = c & 15, c8 = c >> 4;
-        const u4v* src = Dg + ((size_t)blk * BMP + 2 * rp) * NC8 + c8;
-        p0[i] = src[0];
-        p1[i] = src[NC8];
-      }
-    } else {
+    if constexpr (FP8) {
       const u4v* srcd = Dg + (size_t)blk * NCH8;
 #pragma unroll
       for (int i = 0; i < NPF8; ++i) pd[i] = srcd[min(tid + NT * i, NCH8 - 1)];
+    } else {
+      const u4v* srcd = Dg + (size_t)blk * NCHB;
 #pragma unroll
-      for (int i = 0; i < NPF; ++i) {
-        const int c = min(tid + NT * i, NCH - 1);
-        const int l = c >> 2, part = c & 3;
-        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp + (size_t)blk * BMP +
-                                              part * 8);
-      }
+      for (int i = 0; i < NPFB; ++i) pb[i] = srcd[min(tid + NT * i, NCHB - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < NPF; ++i) {
+      const int c = min(tid + NT * i, NCH - 1);
+      const int l = c >> 2, part = c & 3;
+      pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp + (size_t)blk * BMP + part * 8);
     }
     if (tid < BMP) gpre = a.grp[blk * BMP + tid];
   };
@@ -808,26 +793,16 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   auto stage = [&](int buf) {
     if constexpr (!FP8) {
       __bf16* sD16 = reinterpret_cast<__bf16*>(sD[buf]);
-      unsigned* sT32 = reinterpret_cast<unsigned*>(sT[buf]);
 #pragma unroll
-      for (int i = 0; i < NPT; ++i) {
+      for (int i = 0; i < NPFB; ++i) {
         const int c = tid + NT * i;
-        if (NTASK % NT == 0 || c < NTASK) {
-          const int rp = c & 15, c8 = c >> 4;
-          *reinterpret_cast<u4v*>(&sD16[(2 * rp) * DS + 8 * c8]) = p0[i];
-          *reinterpret_cast<u4v*>(&sD16[(2 * rp + 1) * DS + 8 * c8]) = p1[i];
-          // word (dwell 8 c8 + e, points 2 rp .. 2 rp + 1) of the transposed tile
-          // points 2 rp, 2 rp + 1 sit at positions tpos(2 rp), tpos(2 rp) + 1
-          unsigned* dst = sT32 + (trow(8 * c8) >> 1) + (tpos(2 * rp) >> 1);
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            // low halves of both rows, then high halves (byte selects of v_perm)
-            dst[(2 * w) * (TS / 2)] = __builtin_amdgcn_perm(p1[i][w], p0[i][w], 0x05040100u);
-            dst[(2 * w + 1) * (TS / 2)] = __builtin_amdgcn_perm(p1[i][w], p0[i][w], 0x07060302u);
-          }
+        if (NCHB % NT == 0 || c < NCHB) {
+          const int row = c / NC8, c8 = c - row * NC8;
+          *reinterpret_cast<u4v*>(&sD16[row * DS + 8 * c8]) = pb[i];
         }
       }
     } else {
+      // (FP8 rows of Kp + 8 bytes are 8-byte aligned)
 #pragma unroll
       for (int i = 0; i < NPF8; ++i) {
         const int c = tid + NT * i;
@@ -838,15 +813,14 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
           dst[1] = u2v{pd[i][2], pd[i][3]};
         }
       }
+    }
+    // the transposed tile: 80-byte rows, 16-byte aligned chunks
 #pragma unroll
-      for (int i = 0; i < NPF; ++i) {
-        const int c = tid + NT * i;
-        if (NCH % NT == 0 || c < NCH) {
-          const int l = c >> 2, part = c & 3;
-          u2v* dst = reinterpret_cast<u2v*>(&sT[buf][trow(l) + part * 8]);
-          dst[0] = u2v{pt[i][0], pt[i][1]};
-          dst[1] = u2v{pt[i][2], pt[i][3]};
-        }
+    for (int i = 0; i < NPF; ++i) {
+      const int c = tid + NT * i;
+      if (NCH % NT == 0 || c < NCH) {
+        const int l = c >> 2, part = c & 3;
+        *reinterpret_cast<u4v*>(&sT[buf][trow(l) + part * 8]) = pt[i];
       }
     }
     if (tid < BMP) sG[buf][tid] = gpre;

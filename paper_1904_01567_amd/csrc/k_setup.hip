@@ -44,8 +44,17 @@ __device__ inline uint16_t bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Position of point r of a 32-point block in the BF16 / FP8 evaluation's transposed
+// tile (its back-projection operand order): rows 4q .. 4q+3 and
+// 16+4q .. 16+4q+3 of the block at positions 8q .. 8q+7.
+__device__ inline int tpos32(int r) {
+  return r < 16 ? 8 * (r >> 2) + (r & 3) : 8 * ((r - 16) >> 2) + 4 + ((r - 16) & 3);
+}
+
 // BF16 copies of the dose-rate matrix, row-major (points x dwells) for the
-// dose product and dwell-major for the back-projection.
+// dose product and dwell-major for the back-projection, the latter with the
+// points of each 32-point block in the tile order above (Mp is a multiple of
+// 32).
 __global__ void k_cast_bf16(const double* __restrict__ D64, int Mp, int Kp,
                             uint16_t* __restrict__ D, uint16_t* __restrict__ DT) {
   const size_t n = (size_t)Mp * Kp;
@@ -54,7 +63,7 @@ __global__ void k_cast_bf16(const double* __restrict__ D64, int Mp, int Kp,
     const size_t i = idx / Kp, l = idx - i * Kp;
     const uint16_t v = bf16_rne((float)D64[idx]);
     D[idx] = v;
-    DT[l * Mp + i] = v;
+    DT[l * Mp + (i & ~(size_t)31) + tpos32((int)(i & 31))] = v;
   }
 }
 
@@ -72,13 +81,6 @@ __global__ void k_colscale(const double* __restrict__ D64, int Mp, int Kp, float
     __syncthreads();
   }
   if (threadIdx.x == 0) cs[l] = red[0] > 0.0 ? (float)(red[0] / 224.0) : 1.f;
-}
-
-// Position of point r of a 32-point block in the FP8 evaluation's transposed
-// tile (its back-projection operand order): rows 4q .. 4q+3 and
-// 16+4q .. 16+4q+3 of the block at positions 8q .. 8q+7.
-__device__ inline int tpos32(int r) {
-  return r < 16 ? 8 * (r >> 2) + (r & 3) : 8 * ((r - 16) >> 2) + 4 + ((r - 16) & 3);
 }
 
 // FP8 (hardware e4m3 encoding) copy of D_il / s_l, row-major, and the BF16
