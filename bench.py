@@ -323,6 +323,8 @@ def warm_start_compare(args) -> int:
     targets = [1e-1, 3e-2, 1e-2, 3e-3, 1e-3]
     grid = [10, 20, 40, 80, 160, 320, 640, 1280]
     rows = []
+    floors = [float(v) for v in args.warm_floors.split(",")]
+    forms = ["cold", "warm"] + [f"warm_floor{fl:g}" for fl in floors[1:]]
     for h in range(args.heldout):
         idx = 10_000 + h
         case, W = cases.case_learned(idx), cases.weights_learned(idx, args.plans)
@@ -332,14 +334,15 @@ def warm_start_compare(args) -> int:
         pl.optimize(max_iter=6000, dtype="f32acc64")
         F_ref = pl.metrics()["F64"]
         row = {"case": idx}
-        for form in ("cold", "warm"):
+        for form, floor in zip(forms, [None] + floors):
             torch.cuda.synchronize()
             t_start = time.perf_counter()
             if form == "cold":
                 pl.set_weights(W)
             else:
-                use = pl.set_weights_learned(net, W, ws.X_FLOOR)
-                row["learned_start_kept"] = int(use.sum())
+                use = pl.set_weights_learned(net, W, floor)
+                row.setdefault("learned_start_kept", int(use.sum()))
+                row[form + "_kept"] = int(use.sum())
             for k, st in enumerate(ladder):
                 pl.optimize(max_iter=st.max_iter, dtype=st.dtype, eps=DEFAULT_EPS, resume_stopped=k > 0)
             torch.cuda.synchronize()
@@ -362,9 +365,11 @@ def warm_start_compare(args) -> int:
         "heldout": args.heldout,
         "headline_form": {"ladder": DEFAULT_LADDER, "eps": DEFAULT_EPS, "tol_rel_F": TOL_F,
                           "reference": "f32acc64, 6000 steps, uniform start",
-                          "median_ms": {"cold": med("cold", "ms"), "warm": med("warm", "ms")},
+                          "warm_floors": floors,
+                          "median_ms": {f: med(f, "ms") for f in forms},
                           "cases_all_within_tol": {f: int(sum(r[f]["within_tol"] == args.plans for r in rows))
-                                                   for f in ("cold", "warm")},
+                                                   for f in forms},
+                          "median_within_tol": {f: med(f, "within_tol") for f in forms},
                           "median_learned_start_kept": float(np.median([r["learned_start_kept"] for r in rows]))},
         "targets": targets, "rows": rows}), flush=True)
     return 0
@@ -615,6 +620,9 @@ def main(argv=None) -> int:
     ap.add_argument("--warm-start-compare", action="store_true",
                     help="warm-started BF16 form vs plain FP32 L-BFGS, time to equal accuracy")
     ap.add_argument("--train-cases", type=int, default=500)
+    ap.add_argument("--warm-floors", type=str, default="0.001",
+                    help="--warm-start-compare: floors of the learned start (x_hat >= floor, in units of "
+                         "the uniform start's sqrt(t_bar)); the first is the 'warm' form")
     ap.add_argument("--heldout", type=int, default=50)
     ap.add_argument("--grid-cases", type=int, default=10,
                     help="held-out cases that also time the FP32 forms against looser targets")
