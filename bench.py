@@ -58,8 +58,8 @@ EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k
 # the 360 x 20,000 x 1,000 workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (KiB per dispatch, median of the full-batch dispatches) scaled by the same
 # counters on a 256 MiB copy (read x 2.000, write x 1.000); valid only for the
-# kernel source they were taken on (first 16 hex digits of its SHA-256).
-EVAL_TRAFFIC = {"k_eval_sha256": "fab553bb6bee057e", "dtype": "f32acc64", "plans": 1000,
+# kernel code they were taken on (kernel_source_hash: comments left out).
+EVAL_TRAFFIC = {"k_eval_sha256": "6e17fdbe4beb76ed", "dtype": "f32acc64", "plans": 1000,
                 "fetch_kib": 21271.9, "fetch_scale": 262144.0 / 131092.3,
                 "write_kib": 24708.0, "write_scale": 262144.0 / 262144.0}
 ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
@@ -185,13 +185,23 @@ def cpu_baseline(n_plans: int, max_iter: int, eps: float, n_batch: int = 1000):
                        f"threads {threads})")
 
 
-def eval_traffic(dtype: str, plans: int):
-    """Counter-derived HBM bytes per launch, or None when the kernel source,
-    the arithmetic or the batch differs from the one the counters were taken on."""
+def kernel_source_hash(path: str) -> str:
+    """First 16 hex digits of the SHA-256 of a source file's code: line
+    comments and blank lines removed, so that a comment edit does not count
+    as a kernel change."""
     import hashlib
+    import re
+    with open(path) as f:
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in f.read().splitlines()]
+    code = "\n".join(ln for ln in lines if ln.strip())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
+def eval_traffic(dtype: str, plans: int):
+    """Counter-derived HBM bytes per launch, or None when the kernel code,
+    the arithmetic or the batch differs from the one the counters were taken on."""
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_01567_amd", "csrc", "k_eval.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    sha = kernel_source_hash(src)
     t = EVAL_TRAFFIC
     if sha != t["k_eval_sha256"] or dtype != t["dtype"] or plans != t["plans"]:
         return None

@@ -345,16 +345,17 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
 
 // ---------------------------------------------------------------------------
 // MODE_ACC64 (FP32 operands, FP64-accumulated dose, FP64 penalty, FP32
-// back-projection) with 512 threads: two waves per SIMD.  The FP64 matrix op
-// reaches its full rate only when two waves per SIMD issue it, and a wave
-// that holds t and the gradient accumulators of 16 plans over all Kp dwells
-// does not fit in half the register file.  So the 8 waves form 4 plan groups
-// (16 plans each) x 2 dwell halves: each wave forms the partial dose of its
-// dwell half, the two partials of a plan group are added through LDS in a
-// fixed order, both waves evaluate eq. 1 on the sum, and each back-projects
-// onto its own dwell half.  Same software pipeline as the 256-thread kernel
-// (dose product of block b with the back-projection of block b-1, two LDS
-// buffers), with two barriers per block.
+// back-projection), by default with 512 threads: two waves per SIMD.  The
+// FP64 matrix op reaches its full rate only when two waves per SIMD issue it,
+// and a wave that holds t and the gradient accumulators of 16 plans over all
+// Kp dwells does not fit in half the register file.  So the 8 waves form 4
+// plan groups (16 plans each) x 2 dwell halves: each wave forms the partial
+// dose of its dwell half, the partials of a plan group are added through LDS
+// in a fixed order, the waves of the group evaluate eq. 1 on the sum (two of
+// the four rows each) and each back-projects onto its own dwell half.  Per
+// block: the dose product of block b, then the back-projection of block b-1
+// (skipped by a wave whose phi is zero for all its points and plans), on two
+// LDS buffers, with two barriers per block.
 // LDS tile row stride Kp + 16 with the float4 chunk index of row R XORed with
 // (R >> 1) & 3: the back-projection reads 16 columns of rows q + 4r (the FP64
 // op's row order), which that stride puts on opposite bank halves for

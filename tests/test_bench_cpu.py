@@ -29,3 +29,17 @@ def test_host_oracle_timing_line(capsys):
     assert abs(d["s_per_plan"] * cb["value"] - 1.0) < 1e-12
     assert "at most 3 steps; 3 accepted steps in all" in cb["sample"]
     assert cb["host_cpu"]
+
+
+def test_kernel_source_hash_ignores_comments_only(tmp_path):
+    # The traffic figure stays valid across comment edits of the kernel
+    # source, and is dropped for any change of its code.
+    import bench
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("int f(int x) {\n  return x + 1;  // one\n}\n")
+    b.write_text("// a note\nint f(int x) {\n\n  return x + 1;  // another note\n}\n")
+    c.write_text("int f(int x) {\n  return x + 2;  // one\n}\n")
+    assert bench.kernel_source_hash(str(a)) == bench.kernel_source_hash(str(b))
+    assert bench.kernel_source_hash(str(a)) != bench.kernel_source_hash(str(c))
