@@ -599,6 +599,9 @@ def main(argv=None) -> int:
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--plans", type=int, default=1000)
     ap.add_argument("--history", type=int, default=10, help="L-BFGS pairs m")
+    ap.add_argument("--stage-max-ls", type=str, default="30",
+                    help="line-search trials per iteration before LS_FAIL, per ladder stage "
+                         "(comma list; the last value repeats)")
     ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1, 2],
                     help="workgroup shape of the FP64-accumulated kernel (0: 512 threads per "
                          "64 plans, 1: 256 threads per 32 plans, 2: 1,024 threads per 64 plans "
@@ -728,12 +731,15 @@ def main(argv=None) -> int:
                               [f"{stages[-1][0]}:{n}"], "device_ms": ms, "tol": rep}), flush=True)
         return 0
 
+    ls = [int(v) for v in args.stage_max_ls.split(",")]
+    stage_ls = [ls[min(k, len(ls) - 1)] for k in range(len(stages))]
+
     def step(time_kernels=0):
         pl.set_weights(W)
         infos = []
         for k, (dt, cap) in enumerate(stages):
             infos.append(pl.optimize(max_iter=cap, time_kernels=time_kernels, dtype=dt,
-                                     eps=run_eps, resume_stopped=k > 0))
+                                     eps=run_eps, resume_stopped=k > 0, max_ls=stage_ls[k]))
         info = {key: sum(i[key] for i in infos) for key in
                 ("rounds", "device_ms", "eval_ms", "update_ms", "eval_launches", "eval_work",
                  "timed_launches", "timed_work")}
@@ -795,6 +801,7 @@ def main(argv=None) -> int:
                         f"relative objective variation {run_eps:g}",
             "dwells": K, "points": M, "plans": P, "iterations": iters, "eps": run_eps,
             "lbfgs_history": args.history, "stages": [f"{d}:{n}" for d, n in stages],
+            "stage_max_ls": stage_ls,
         },
         "tolerance": {"rel_F_excess": TOL_F, "V100_pp": TOL_V100, "check": tol},
         "nondominated_fraction": nd_frac,
