@@ -104,7 +104,7 @@ struct gmco_ctx {
   bool case_loaded = false;
   bool has_points = false;  // point positions were given (features need them)
   int P = 0;              // current batch, 0 = none
-  int* host_count = nullptr;  // pinned mirror of the active counter
+  int* host_count = nullptr;  // pinned copies of the running-plan count, one per block parity
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipStream_t gstream = nullptr;  // library-owned stream for graph capture
   hipEvent_t gev = nullptr;
