@@ -135,7 +135,8 @@ typedef struct {
                          rising precision form a precision ladder on one state. */
   int per_case_launches; /* gmco_optimize_many only: 0 groups the cases (per round, one
                          evaluation launch per padded dwell count and dtype, one
-                         reduction launch, one update launch per update shape);
+                         update launch per update shape, which also sums each
+                         case's gradient partials);
                          1 issues every case's kernels as launches of their own */
 } gmco_run;
 

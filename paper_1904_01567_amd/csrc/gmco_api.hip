@@ -24,7 +24,7 @@ struct Layout {
   size_t D64, D32, Dlp, DTlp, colscale, grp, perm, stage, gparams, volume, goff, gcnt, counts, t_bar;
   size_t gorg, D64d, dstage, dperm, doff, dcnt;
   size_t Wst, t0st, xst, Fst, gst;
-  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, Gsum, active, work, flag, slot, rt,
+  size_t wn, W64, x, g, dir, xt, xe, Sh, Yh, rho, ps, Gpart, Fpart, active, work, flag, slot, rt,
       split_tab;
   size_t t64, d64, metrics, hist, feat, sel;
   size_t mlpX, mlpY, Fu, usewarm, nwarm;
@@ -232,7 +232,6 @@ Layout make_layout(const Dims& d, int G, int m, int dtype, int Pmax) {
   L.ps = take((size_t)d.Pp * sizeof(PlanState));
   L.Gpart = take((size_t)d.grid_cap * kPT * d.Kp * 4);
   L.Fpart = take((size_t)d.grid_cap * kPT * 8);
-  L.Gsum = take(PK * 4);
   L.flag = take((size_t)d.Pp * 4);
   L.slot = take((size_t)d.Pp * 4);
   L.rt = take(sizeof(RoundTable));
@@ -314,7 +313,7 @@ UpdateArgs update_args(gmco_ctx* c, const gmco_run* r) {
   const Layout& L = c->lay;
   const Dims& d = c->dim;
   UpdateArgs u{};
-  u.Gsum = c->at<float>(L.Gsum);
+  u.Gpart = c->at<float>(L.Gpart);
   u.Fpart = c->at<double>(L.Fpart);
   u.x = c->at<float>(L.x);
   u.g = c->at<float>(L.g);
@@ -792,7 +791,6 @@ int gmco_optimize(gmco_ctx* c, const gmco_run* r, gmco_run_info* info) {
         GMCO_HIP(c, hipEventRecord(e[4 * i + 1], c->stream));
         GMCO_HIP(c, hipEventRecord(e[4 * i + 2], c->stream));
       }
-      GMCO_HIP(c, launch_reduce_g(a.Gpart, a.rt, d.Pp, d.Kp, c->at<float>(L.Gsum), c->stream));
       GMCO_HIP(c, launch_update(u, c->stream));
       if (tk) {
         GMCO_HIP(c, hipEventRecord(e[4 * i + 3], c->stream));
@@ -894,8 +892,6 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
   EvalArgs* d_eargs = nullptr;
   int* d_start = nullptr;
   UpdateArgs* d_uargs = nullptr;
-  ReduceArgs* d_rargs = nullptr;
-  long long red_threads = 1;
   if (grouped) {
     auto bucket_of = [](std::vector<Bucket>& v, int k0, int k1, int k2) -> Bucket& {
       for (Bucket& b : v)
@@ -930,15 +926,9 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
         b.pp_max = std::max(b.pp_max, ctxs[i]->dim.Pp);
       }
     }
-    std::vector<ReduceArgs> hr(n);
-    for (int i = 0; i < n; ++i) {
-      gmco_ctx* c = ctxs[i];
-      hr[i] = ReduceArgs{as[i].Gpart, as[i].rt, c->at<float>(c->lay.Gsum), c->dim.Kp, 0};
-      red_threads = std::max(red_threads, (long long)c->dim.Pp * (c->dim.Kp / 4));
-    }
     const size_t be = align256(he.size() * sizeof(EvalArgs)), bs = align256(hs.size() * sizeof(int));
-    const size_t bu = align256(hu.size() * sizeof(UpdateArgs)), br = align256(hr.size() * sizeof(ReduceArgs));
-    if (hipMalloc(&dtab, be + bs + bu + br) != hipSuccess) {
+    const size_t bu = align256(hu.size() * sizeof(UpdateArgs));
+    if (hipMalloc(&dtab, be + bs + bu) != hipSuccess) {
       dtab = nullptr;
       return fail(c0, GMCO_ENOMEM, "argument tables of the grouped launches");
     }
@@ -946,11 +936,9 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     d_eargs = reinterpret_cast<EvalArgs*>(base);
     d_start = reinterpret_cast<int*>(base + be);
     d_uargs = reinterpret_cast<UpdateArgs*>(base + be + bs);
-    d_rargs = reinterpret_cast<ReduceArgs*>(base + be + bs + bu);
     GMCO_HIP(c0, hipMemcpyAsync(d_eargs, he.data(), he.size() * sizeof(EvalArgs), hipMemcpyHostToDevice, st));
     GMCO_HIP(c0, hipMemcpyAsync(d_start, hs.data(), hs.size() * sizeof(int), hipMemcpyHostToDevice, st));
     GMCO_HIP(c0, hipMemcpyAsync(d_uargs, hu.data(), hu.size() * sizeof(UpdateArgs), hipMemcpyHostToDevice, st));
-    GMCO_HIP(c0, hipMemcpyAsync(d_rargs, hr.data(), hr.size() * sizeof(ReduceArgs), hipMemcpyHostToDevice, st));
     GMCO_HIP(c0, hipStreamSynchronize(st));  // the host tables above are freed on return
   }
   auto issue_round = [&](long long rd) -> int {
@@ -958,7 +946,6 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
       for (const Bucket& b : eb)
         GMCO_HIP(c0, launch_eval_grouped(d_eargs + b.off, d_start + b.soff, (int)b.cases.size(), b.grid, b.key0,
                                          b.key1, b.key2, st));
-      GMCO_HIP(c0, launch_reduce_g_grouped(d_rargs, n, red_threads, st));
       for (const Bucket& b : ub)
         GMCO_HIP(c0, launch_update_grouped(d_uargs + b.off, (int)b.cases.size(), b.key0, b.pp_max, b.key1,
                                            (int)rd, st));
@@ -967,7 +954,6 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* r, gmco_run
     for (int i = 0; i < n; ++i) {
       us[i].round = (int)rd;
       GMCO_HIP(ctxs[i], launch_eval(as[i], dtypes[i], st));
-      GMCO_HIP(ctxs[i], launch_reduce_g(as[i].Gpart, as[i].rt, ctxs[i]->dim.Pp, ctxs[i]->dim.Kp, ctxs[i]->at<float>(ctxs[i]->lay.Gsum), st));
       GMCO_HIP(ctxs[i], launch_update(us[i], st));
     }
     return GMCO_OK;

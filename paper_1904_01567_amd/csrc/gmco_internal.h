@@ -125,7 +125,7 @@ struct EvalArgs {
 };
 
 struct UpdateArgs {
-  const float* Gsum;      // [Pp][Kp] summed gradient partials by compact column
+  const float* Gpart;     // split-M gradient partials [S][ntiles * kPT][Kp] by compact column
   const double* Fpart;
   float* x;       // [Pp][Kp] current iterate
   float* g;       // [Pp][Kp] gradient at x
@@ -145,17 +145,10 @@ struct UpdateArgs {
   int round;
 };
 
-// Arguments of one case's split-partial reduction (grouped launches).
-struct ReduceArgs {
-  const float* Gpart;
-  const RoundTable* rt;
-  float* Gsum;
-  int Kp, pad;
-};
-
 // Update kernel lane layout: groups of four dwells per lane, E values per
 // lane (4 up to 256 padded dwells, 8 up to 512).
 __host__ __device__ constexpr int update_width(int Kp) { return Kp <= 256 ? 4 : (Kp <= 512 ? 8 : 0); }
+constexpr int kKpMax = 512;  // largest padded dwell count the update supports
 
 // ---- launchers (each defined next to its kernels) ----
 hipError_t launch_dose_rate(const double* dwell_xyz, const double* pt_xyz, const double* user_D,
@@ -177,17 +170,14 @@ hipError_t launch_eval(const EvalArgs& a, int dtype, hipStream_t st);
 // of 8), its arguments args[c] (device arrays, n entries / n + 1 starts).
 hipError_t launch_eval_grouped(const EvalArgs* args, const int* start, int n, int grid, int Kp, int dtype,
                                int lp_shape, hipStream_t st);
-// Update / reduction of n cases in one launch (cases of one update width E
-// for the update); grids sized for the largest case.
+// Update of n cases in one launch (cases of one update width E); the grid is
+// sized for the largest case.
 hipError_t launch_update_grouped(const UpdateArgs* args, int n, int E, int Pp_max, int m, int round,
                                  hipStream_t st);
-hipError_t launch_reduce_g_grouped(const ReduceArgs* args, int n, long long max_threads, hipStream_t st);
 hipError_t launch_update(const UpdateArgs& a, hipStream_t st);
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
                               int P, int Pp, int K, int Kp, double* F, double* g,
                               hipStream_t st);
-hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
-                           hipStream_t st);
 hipError_t launch_resume(PlanState* ps, const float* x, float* xt, int* flag, int Pp, int Kp,
                          int max_iter, int resume_stopped, hipStream_t st);
 hipError_t launch_export_t(const float* x, int P, int K, int Kp, double* t64, int Kp_out,

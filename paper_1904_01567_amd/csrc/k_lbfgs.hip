@@ -129,14 +129,74 @@ __device__ inline void store_vec(float* __restrict__ dst, int lane, int Kp, cons
   }
 }
 
+// Sum over the S split-M partials of one float4 of a gradient row, in split
+// order (up to 16 loads in flight); stride4 = float4 between splits.
+__device__ inline float4 sum_partials(const float4* __restrict__ src, size_t stride4, int S) {
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  int s = 0;
+  for (; s + 16 <= S; s += 16) {
+    float4 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = src[(s + u) * stride4];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      acc.x += v[u].x;
+      acc.y += v[u].y;
+      acc.z += v[u].z;
+      acc.w += v[u].w;
+    }
+  }
+  for (; s + 8 <= S; s += 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(s + u) * stride4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc.x += v[u].x;
+      acc.y += v[u].y;
+      acc.z += v[u].z;
+      acc.w += v[u].w;
+    }
+  }
+  for (; s < S; ++s) {
+    const float4 v = src[s * stride4];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  return acc;
+}
+
+template <int E>
+__device__ inline void load_vec_lds(const float* src, int lane, int Kp, float (&v)[E]) {
+#pragma unroll
+  for (int c = 0; c < E / 4; ++c) {
+    const int e = 4 * lane + 256 * c;
+    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e < Kp) t = *reinterpret_cast<const float4*>(src + e);
+    v[4 * c + 0] = t.x;
+    v[4 * c + 1] = t.y;
+    v[4 * c + 2] = t.z;
+    v[4 * c + 3] = t.w;
+  }
+}
+
 // MH = register capacity for history pairs (MH >= m).  The pairs are held in
 // registers in age order (0 = newest) so every loop index is a compile-time
 // constant; all their loads are issued together before the recursion.
+// One workgroup of two wavefronts per plan.  Wavefront 1 sums the split-M
+// gradient partials of the plan's compact column, in split order, into LDS
+// (so the round needs no separate reduction launch) while wavefront 0 loads
+// the plan's vectors and history; wavefront 0 then advances the plan with G
+// from LDS.  (Two wavefronts of up to 256 VGPRs per plan keep a 1,024-plan
+// batch resident at once.)
 template <int E, int MH>
-__device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
+__device__ inline void update_plans(const UpdateArgs& a, int p, int round) {
+  __shared__ __attribute__((aligned(16))) float sGs[kKpMax];
+  const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int p = bx * 4 + (threadIdx.x >> 6);
-  if (bx == 0 && threadIdx.x == 0) a.active_count[(round + 1) & 1] = 0;
+  if (p == 0 && threadIdx.x == 0) a.active_count[(round + 1) & 1] = 0;
   if (p >= a.Pp) return;
   const int Kp = a.Kp;
   const int m = a.m;
@@ -144,12 +204,22 @@ __device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
 
   // Two levels of loads: first the plan's state with the round's shape and
   // the plan's compact column (small, recently written), then, for a running
-  // plan only, its vectors, history and gradient sums all at once.  A
-  // stopped plan costs one 64-byte read.
+  // plan only, its vectors, history and gradient partials all at once.  A
+  // stopped plan costs one 64-byte read per wavefront.
   PlanState st = a.ps[p];
   const RoundTable rt = *a.rt;
   const size_t col = (size_t)a.slot[p];
-  if (!state_active(st.status)) return;
+  if (!state_active(st.status)) return;  // (the same for the whole workgroup)
+  const size_t stride = (size_t)rt.ntiles * kPT;
+  if (wave == 1) {
+    const int nq = Kp / 4;  // float4 of a row (Kp at most 512: two per lane)
+    const float4* src = reinterpret_cast<const float4*>(a.Gpart + col * Kp);
+#pragma unroll
+    for (int c = lane; c < kKpMax / 4; c += 64)
+      if (c < nq) *reinterpret_cast<float4*>(&sGs[4 * c]) = sum_partials(src + c, stride * Kp / 4, rt.S);
+  }
+  __syncthreads();
+  if (wave > 0) return;
   float xt[E], gt[E], x[E], g[E], d[E];
   float G[E];
   load_vec(a.xt + row, lane, Kp, xt);
@@ -182,9 +252,8 @@ __device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
       load_vec(Yd, lane, Kp, ohy[i]);
     }
   }
-  // gradient partials of this round's compact column, summed by k_reduce_g
-  const size_t stride = (size_t)rt.ntiles * kPT;
-  load_vec(a.Gsum + col * Kp, lane, Kp, G);
+  // gradient of this round's compact column, summed above
+  load_vec_lds(sGs, lane, Kp, G);
   // split partials of F: one load per lane, then a fixed-order wave sum
   double fpart = 0.0;
   for (int s = lane; s < rt.S; s += 64) fpart += a.Fpart[s * stride + col];
@@ -332,20 +401,20 @@ __device__ inline void update_plans(const UpdateArgs& a, int bx, int round) {
 }
 
 template <int E, int MH>
-__global__ __launch_bounds__(256) void k_update(UpdateArgs a) {
+__global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
   update_plans<E, MH>(a, blockIdx.x, a.round);
 }
 
 // Grouped form: case blockIdx.y of n, its arguments from args (their round
 // field is not used; all cases are in the same round).
 template <int E, int MH>
-__global__ __launch_bounds__(256) void k_update_grouped(const UpdateArgs* __restrict__ args, int round) {
+__global__ __launch_bounds__(128) void k_update_grouped(const UpdateArgs* __restrict__ args, int round) {
   update_plans<E, MH>(args[blockIdx.y], blockIdx.x, round);
 }
 
 template <int E>
 hipError_t launch_update_e(const UpdateArgs& a, hipStream_t st) {
-  const dim3 grid((a.Pp + 3) / 4), block(256);
+  const dim3 grid(a.Pp), block(128);
   if (a.m <= 4) hipLaunchKernelGGL((k_update<E, 4>), grid, block, 0, st, a);
   else if (a.m <= 10) hipLaunchKernelGGL((k_update<E, 10>), grid, block, 0, st, a);
   else if (a.m <= 16) hipLaunchKernelGGL((k_update<E, 16>), grid, block, 0, st, a);
@@ -356,73 +425,12 @@ hipError_t launch_update_e(const UpdateArgs& a, hipStream_t st) {
 template <int E>
 hipError_t launch_update_grouped_e(const UpdateArgs* args, int n, int Pp_max, int m, int round,
                                    hipStream_t st) {
-  const dim3 grid((Pp_max + 3) / 4, n), block(256);
+  const dim3 grid(Pp_max, n), block(128);
   if (m <= 4) hipLaunchKernelGGL((k_update_grouped<E, 4>), grid, block, 0, st, args, round);
   else if (m <= 10) hipLaunchKernelGGL((k_update_grouped<E, 10>), grid, block, 0, st, args, round);
   else if (m <= 16) hipLaunchKernelGGL((k_update_grouped<E, 16>), grid, block, 0, st, args, round);
   else hipLaunchKernelGGL((k_update_grouped<E, GMCO_MAX_HISTORY>), grid, block, 0, st, args, round);
   return hipGetLastError();
-}
-
-// Sum of the split-M gradient partials of every compact column, in split
-// order: one thread per (column, 4 dwells), so the sum has the whole chip's
-// parallelism however many splits a round uses.
-__device__ inline void reduce_g(const float* __restrict__ Gpart, const RoundTable* rt, int Kp,
-                                float* __restrict__ Gsum, int bx) {
-  const RoundTable r = *rt;
-  const int nq = Kp / 4;
-  const long long idx = (long long)bx * 256 + threadIdx.x;
-  const int j = (int)(idx / nq);
-  const int c = (int)(idx - (long long)j * nq);
-  if (j >= r.nact) return;
-  const size_t stride = (size_t)r.ntiles * kPT * Kp;
-  const float4* src = reinterpret_cast<const float4*>(Gpart + (size_t)j * Kp) + c;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  int s = 0;
-  // up to 16 loads in flight per thread, summed in split order
-  for (; s + 16 <= r.S; s += 16) {
-    float4 v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = src[(s + u) * stride / 4];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      acc.x += v[u].x;
-      acc.y += v[u].y;
-      acc.z += v[u].z;
-      acc.w += v[u].w;
-    }
-  }
-  for (; s + 8 <= r.S; s += 8) {
-    float4 v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[(s + u) * stride / 4];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc.x += v[u].x;
-      acc.y += v[u].y;
-      acc.z += v[u].z;
-      acc.w += v[u].w;
-    }
-  }
-  for (; s < r.S; ++s) {
-    const float4 v = src[s * stride / 4];
-    acc.x += v.x;
-    acc.y += v.y;
-    acc.z += v.z;
-    acc.w += v.w;
-  }
-  reinterpret_cast<float4*>(Gsum + (size_t)j * Kp)[c] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_reduce_g(const float* __restrict__ Gpart, const RoundTable* rt,
-                                                  int Kp, float* __restrict__ Gsum) {
-  reduce_g(Gpart, rt, Kp, Gsum, blockIdx.x);
-}
-
-// Grouped form: case blockIdx.y.
-__global__ __launch_bounds__(256) void k_reduce_g_grouped(const ReduceArgs* __restrict__ args) {
-  const ReduceArgs& a = args[blockIdx.y];
-  reduce_g(a.Gpart, a.rt, a.Kp, a.Gsum, blockIdx.x);
 }
 
 // Partial reduction for a stand-alone evaluation: F = sum_s Fpart, g = 4 x G.
@@ -479,21 +487,6 @@ hipError_t launch_update_grouped(const UpdateArgs* args, int n, int E, int Pp_ma
   if (E == 4) return launch_update_grouped_e<4>(args, n, Pp_max, m, round, st);
   if (E == 8) return launch_update_grouped_e<8>(args, n, Pp_max, m, round, st);
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_reduce_g_grouped(const ReduceArgs* args, int n, long long max_threads, hipStream_t st) {
-  const dim3 grid((unsigned)((max_threads + 255) / 256), n);
-  hipLaunchKernelGGL(k_reduce_g_grouped, grid, dim3(256), 0, st, args);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_g(const float* Gpart, const RoundTable* rt, int Pp, int Kp, float* Gsum,
-                           hipStream_t st) {
-  if (Kp % 4 != 0) return hipErrorInvalidValue;
-  const long long threads = (long long)Pp * (Kp / 4);
-  const dim3 grid((unsigned)((threads + 255) / 256));
-  hipLaunchKernelGGL(k_reduce_g, grid, dim3(256), 0, st, Gpart, rt, Kp, Gsum);
-  return hipGetLastError();
 }
 
 hipError_t launch_finish_eval(const float* Gpart, const double* Fpart, const float* x, int S,
