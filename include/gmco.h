@@ -308,7 +308,9 @@ typedef struct {
   int split;     /* point-range splits of a full-batch round */
   int tuned;     /* 1: split set by the autotuner or the caller */
   int lp_shape;  /* workgroup shape.  BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32
-                    (Kp <= 384).  FP32 operands with FP64-accumulated dose: 0 = 512
+                    (Kp <= 384), 2 = 4 x 32 plans in two roles of 4 wavefronts, dose
+                    product with eq. 1 and back-projection of the previous block
+                    (Kp <= 384); all three give the same bits.  FP32 operands with FP64-accumulated dose: 0 = 512
                     threads per 64-plan tile (dwell halves), 1 = 256 threads per 32
                     plans (two workgroups per compute unit), 2 = 1,024 threads per
                     64-plan tile (dwell quarters, four waves per SIMD; Kp a

@@ -533,6 +533,9 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
     c->ws_bytes = L.total;
   }
   c->dim = d;
+  // BF16: the role-split workgroup where it exists (measured faster at the
+  // paper-scale case; FP8 keeps shape 0, which measured as fast)
+  if (c->dtype == GMCO_DTYPE_BF16 && lp_shape_ok(d.Kp, 2)) c->dim.lp_shape = 2;
   c->lay = L;
   c->G = G;
   c->O = O;
@@ -1143,7 +1146,8 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
       cand.push_back(s);
   std::vector<int> shapes = {0};
   if ((lp && lp_shape_ok(d.Kp, 1)) || dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(1);
-  if (dtype == GMCO_DTYPE_F32_ACC64 && acc_quarters_ok(d.Kp)) shapes.push_back(2);
+  if ((lp && lp_shape_ok(d.Kp, 2)) || (dtype == GMCO_DTYPE_F32_ACC64 && acc_quarters_ok(d.Kp)))
+    shapes.push_back(2);
   int& shape_ref = lp ? d.lp_shape : d.acc_shape;  // (unused by the plain FP32 kernel)
   const int orig_s = S_dense, orig_x = xcd, orig_shape = shape_ref;
   int best = orig_s, best_x = orig_x, best_shape = orig_shape;

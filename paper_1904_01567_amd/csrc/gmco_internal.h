@@ -18,12 +18,16 @@ constexpr int kPT = 64;   // plans per tile of the evaluation (one FP32 workgrou
 // double-buffered LDS tile; at Kp = 416 four wavefronts of 32 plans; above,
 // four of 16 (the registers of 32 plans no longer fit).  Shape 1 (up to
 // Kp = 384, an autotuner candidate): four wavefronts of 32 plans, one per
-// SIMD, each LDS operand feeding twice the matrix ops.  Both shapes of a Kp
-// cover the same plan tiles (lp_tiles), so the grid does not depend on the
-// shape.
-__host__ __device__ constexpr bool lp_shape_ok(int Kp, int shape) { return shape == 0 || (shape == 1 && Kp <= 384); }
+// SIMD, each LDS operand feeding twice the matrix ops.  Shape 2 (up to
+// Kp = 384, an autotuner candidate): eight wavefronts in two roles over four
+// groups of 32 plans, the dose product with eq. 1 in one, the back-projection
+// of the previous block in the other.  All shapes of a Kp cover the same
+// plan tiles (lp_tiles), so the grid does not depend on the shape.
+__host__ __device__ constexpr bool lp_shape_ok(int Kp, int shape) {
+  return shape == 0 || ((shape == 1 || shape == 2) && Kp <= 384);
+}
 __host__ __device__ constexpr int lp_threads(int Kp, int shape = 0) {
-  return (Kp <= 384 && shape == 0) ? 512 : 256;
+  return (Kp <= 384 && (shape == 0 || shape == 2)) ? 512 : 256;
 }
 __host__ __device__ constexpr int lp_halves(int Kp, int shape = 0) {
   return (Kp == 416 || (Kp <= 384 && shape == 1)) ? 2 : 1;

@@ -645,6 +645,109 @@ struct LpOp<true> {
   static __device__ inline f4v mma(long a, long b, f4v c) { return mfma_fp8(a, b, c); }
 };
 
+// B operand of the dose product for one column of 16 plans: lane (q, n)
+// holds t = x^2 of plan `plan` (-1: an empty column, t = 0) at dwells
+// 32 k + 8 q + e.  FP8: the scaled times t_l s_l / u with the plan's scale u
+// (the maximum over the plan's dwells / 224); BF16: u = 1.
+template <int KP, bool FP8>
+__device__ inline void lp_t_operand(const EvalArgs& a, int plan, int q, typename LpOp<FP8>::type (&tb)[KP / 32],
+                                    float& u) {
+  constexpr int NK32 = KP / 32;
+  const bool pv = plan >= 0;
+  const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
+  u = 1.f;
+  if constexpr (!FP8) {
+#pragma unroll
+    for (int k = 0; k < NK32; ++k) {
+      const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
+      const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
+      tb[k][0] = (__bf16)(pv ? x0.x * x0.x : 0.f);
+      tb[k][1] = (__bf16)(pv ? x0.y * x0.y : 0.f);
+      tb[k][2] = (__bf16)(pv ? x0.z * x0.z : 0.f);
+      tb[k][3] = (__bf16)(pv ? x0.w * x0.w : 0.f);
+      tb[k][4] = (__bf16)(pv ? x1.x * x1.x : 0.f);
+      tb[k][5] = (__bf16)(pv ? x1.y * x1.y : 0.f);
+      tb[k][6] = (__bf16)(pv ? x1.z * x1.z : 0.f);
+      tb[k][7] = (__bf16)(pv ? x1.w * x1.w : 0.f);
+    }
+  } else {
+    // scaled dwell times t_l s_l, their per-plan maximum, then FP8 fragments
+    float ts[NK32][8];
+    float tmax = 0.f;
+#pragma unroll
+    for (int k = 0; k < NK32; ++k) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int l = 32 * k + 8 * q + e;
+        const float xv = xrow[l];
+        ts[k][e] = pv ? xv * xv * a.colscale[l] : 0.f;
+        tmax = fmaxf(tmax, ts[k][e]);
+      }
+    }
+    tmax = fmaxf(tmax, __shfl_xor(tmax, 16));
+    tmax = fmaxf(tmax, __shfl_xor(tmax, 32));
+    u = tmax > 0.f ? tmax / 224.f : 1.f;
+    const float inv_u = 1.f / u;
+#pragma unroll
+    for (int k = 0; k < NK32; ++k) {
+      const unsigned lo = pack_fp8x4(ts[k][0] * inv_u, ts[k][1] * inv_u, ts[k][2] * inv_u, ts[k][3] * inv_u);
+      const unsigned hi = pack_fp8x4(ts[k][4] * inv_u, ts[k][5] * inv_u, ts[k][6] * inv_u, ts[k][7] * inv_u);
+      tb[k] = (long)(((unsigned long)hi << 32) | lo);
+    }
+  }
+}
+
+// Eq. 1 epilogue of one 32-point block for NH columns of 16 plans
+// (col0 + 16 h + n): from the dose accumulators (points 4 q + r and
+// 16 + 4 q + r) to phi in the back-projection's operand order, adding each
+// column's penalties to facc (one FP64 addition per block).
+template <int NH, bool FP8>
+__device__ inline void lp_epilogue(const f4v (&acc)[NH][2], const float (&u)[NH], const int* cG,
+                                   const float4* sP, const float* sW, int col0, int lane, bf8v (&phi)[NH],
+                                   double (&facc)[NH]) {
+  constexpr int BMP = 32;
+  const int q = lane >> 4, n = lane & 15;
+  float fblk[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) fblk[h] = 0.f;
+  // The points are stored grouped by structure, so most blocks hold a
+  // single structure: then the eq. 1 row and the weight w_j / N_j are the
+  // same for all points of the block and are read once.
+  const int g0 = cG[0];
+  if (__all(cG[lane & (BMP - 1)] == g0)) {
+    const float4 pr = sP[g0];
+    float4 pw[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const float w = g0 < kGmax ? sW[(col0 + 16 * h + n) * kGmax + g0] : 0.f;
+      pw[h] = make_float4(w * pr.x, pr.y, pr.z, w * pr.w);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
+        if constexpr (FP8) d *= u[h];
+        phi[h][e] = penalty_lp(d, pw[h], fblk[h]);
+      }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int gi = cG[e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4)];
+      const float4 pr = sP[gi];
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
+        if constexpr (FP8) d *= u[h];
+        const float w = gi < kGmax ? sW[(col0 + 16 * h + n) * kGmax + gi] : 0.f;
+        phi[h][e] = penalty_lp(d, make_float4(w * pr.x, pr.y, pr.z, w * pr.w), fblk[h]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < NH; ++h) facc[h] += (double)fblk[h];
+}
+
 template <int KP, bool FP8, int SHAPE>
 __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   typedef typename LpOp<FP8>::type op_t;
@@ -705,53 +808,7 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
   op_t tb[NH][NK32];
   float u[NH];
 #pragma unroll
-  for (int h = 0; h < NH; ++h) {
-    u[h] = 1.f;
-    const int plan = sPlan[16 * (NH * wave + h) + n];
-    const bool pv = plan >= 0;
-    const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
-    if constexpr (!FP8) {
-#pragma unroll
-      for (int k = 0; k < NK32; ++k) {
-        const float4 x0 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q);
-        const float4 x1 = *reinterpret_cast<const float4*>(xrow + 32 * k + 8 * q + 4);
-        tb[h][k][0] = (__bf16)(pv ? x0.x * x0.x : 0.f);
-        tb[h][k][1] = (__bf16)(pv ? x0.y * x0.y : 0.f);
-        tb[h][k][2] = (__bf16)(pv ? x0.z * x0.z : 0.f);
-        tb[h][k][3] = (__bf16)(pv ? x0.w * x0.w : 0.f);
-        tb[h][k][4] = (__bf16)(pv ? x1.x * x1.x : 0.f);
-        tb[h][k][5] = (__bf16)(pv ? x1.y * x1.y : 0.f);
-        tb[h][k][6] = (__bf16)(pv ? x1.z * x1.z : 0.f);
-        tb[h][k][7] = (__bf16)(pv ? x1.w * x1.w : 0.f);
-      }
-    } else {
-      // scaled dwell times t_l s_l, their per-plan maximum, then FP8 fragments
-      float ts[NK32][8];
-      float tmax = 0.f;
-#pragma unroll
-      for (int k = 0; k < NK32; ++k) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int l = 32 * k + 8 * q + e;
-          const float xv = xrow[l];
-          ts[k][e] = pv ? xv * xv * a.colscale[l] : 0.f;
-          tmax = fmaxf(tmax, ts[k][e]);
-        }
-      }
-      tmax = fmaxf(tmax, __shfl_xor(tmax, 16));
-      tmax = fmaxf(tmax, __shfl_xor(tmax, 32));
-      u[h] = tmax > 0.f ? tmax / 224.f : 1.f;
-      const float inv_u = 1.f / u[h];
-#pragma unroll
-      for (int k = 0; k < NK32; ++k) {
-        const unsigned lo = pack_fp8x4(ts[k][0] * inv_u, ts[k][1] * inv_u, ts[k][2] * inv_u,
-                                       ts[k][3] * inv_u);
-        const unsigned hi = pack_fp8x4(ts[k][4] * inv_u, ts[k][5] * inv_u, ts[k][6] * inv_u,
-                                       ts[k][7] * inv_u);
-        tb[h][k] = (long)(((unsigned long)hi << 32) | lo);
-      }
-    }
-  }
+  for (int h = 0; h < NH; ++h) lp_t_operand<KP, FP8>(a, sPlan[16 * (NH * wave + h) + n], q, tb[h], u[h]);
   f4v gacc[NH][NK16];
 #pragma unroll
   for (int h = 0; h < NH; ++h)
@@ -868,46 +925,8 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
       }
     }
     // ---- penalty epilogue ----
-    // The points are stored grouped by structure, so most blocks hold a
-    // single structure: then the eq. 1 row and the weight w_j / N_j are the
-    // same for all points of the block and are read once.
     bf8v phi[NH];
-    float fblk[NH];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) fblk[h] = 0.f;
-    const int g0 = cG[0];
-    if (__all(cG[lane & (BMP - 1)] == g0)) {
-      const float4 pr = sP[g0];
-      float4 pw[NH];
-#pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        const float w = g0 < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + g0] : 0.f;
-        pw[h] = make_float4(w * pr.x, pr.y, pr.z, w * pr.w);
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
-          if constexpr (FP8) d *= u[h];
-          phi[h][e] = penalty_lp(d, pw[h], fblk[h]);
-        }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gi = cG[e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4)];
-        const float4 pr = sP[gi];
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          float d = e < 4 ? acc[h][0][e] : acc[h][1][e - 4];
-          if constexpr (FP8) d *= u[h];
-          const float w = gi < kGmax ? sW[(16 * (NH * wave + h) + n) * kGmax + gi] : 0.f;
-          phi[h][e] = penalty_lp(d, make_float4(w * pr.x, pr.y, pr.z, w * pr.w), fblk[h]);
-        }
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < NH; ++h) facc[h] += (double)fblk[h];
+    lp_epilogue<NH, FP8>(acc, u, cG, sP, sW, 16 * NH * wave, lane, phi, facc);
     // ---- back-projection over the 32 points ----
 #pragma unroll
     for (int k = 0; k < NK16; ++k) {
@@ -937,6 +956,218 @@ __device__ inline void eval_lp(const EvalArgs& a, int bid) {
             make_float4(gacc[h][k][0], gacc[h][k][1], gacc[h][k][2], gacc[h][k][3]);
       }
       if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = f;
+    }
+  }
+}
+
+// Workgroup shape 2 (Kp <= 384): the same 128 plans as shape 0, as four
+// column groups of 32 plans, with two roles of four wavefronts (one of each
+// per SIMD).  Waves 0-3 run the dose product and the eq. 1 epilogue of block
+// b for their group (each D operand read from LDS feeds two matrix ops), pass
+// phi to the back-projection through LDS and stage the next tiles; waves 4-7
+// back-project block b - 1 for the same group (each D^T operand read feeds
+// two matrix ops).  So every SIMD holds one wavefront of each role, and the
+// epilogue and staging of one overlap the matrix ops of the other.  Per column
+// the arithmetic and its order are those of shape 0, so the results are
+// bitwise the same.
+template <int KP, bool FP8>
+__device__ inline void eval_lp_ws(const EvalArgs& a, int bid) {
+  typedef typename LpOp<FP8>::type op_t;
+  constexpr int BMP = 32;                      // points per block
+  constexpr int DS = FP8 ? KP + 8 : KP + 16;   // D tile row stride (as shape 0)
+  constexpr int TS = BMP + 8;                  // transposed tile row stride
+  constexpr int TSZ = KP * TS;
+  constexpr int NK32 = KP / 32;
+  constexpr int NK16 = KP / 16;
+  constexpr int NT = 512, NW = 8, NG = 4;      // NG column groups of 32 plans
+  constexpr int NTS = 256;                     // threads per role
+  constexpr int NCOL = NG * 32;
+  static_assert(KP <= 384 && NCOL == lp_tiles(KP) * kPT, "workgroup of whole plan tiles");
+  constexpr int NC8 = KP / 8;                  // 16-byte chunks of a BF16 row
+  constexpr int NCH = BMP * KP / 8;            // 16-byte chunks of a BF16 tile
+  constexpr int NCH8 = BMP * KP / 16;          // 16-byte chunks of an FP8 tile
+  constexpr int NCHD = FP8 ? NCH8 : NCH;
+  constexpr int NPD = (NCHD + NTS - 1) / NTS;
+  constexpr int NPT = (NCH + NTS - 1) / NTS;
+  constexpr int SDB = BMP * DS * (FP8 ? 1 : 2);
+
+  __shared__ __attribute__((aligned(16))) unsigned char sD[2][SDB];
+  __shared__ __attribute__((aligned(16))) __bf16 sT[2][TSZ];
+  __shared__ bf8v sPhi[2][NG][2][64];  // phi of a block, per group and 16-plan half
+  __shared__ int sG[2][BMP];
+  __shared__ float sW[NCOL * kGmax];
+  __shared__ int sPlan[NCOL];
+  __shared__ int sScan[NW];
+  __shared__ float4 sP[kGmax + 1];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+  const int grp = wave & 3;
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j <= kGmax; ++j) sP[j] = a.gt.prm[j];
+  }
+  int s, S, stride, j0;  // (tile_setup ends with a barrier)
+  if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
+  const int nb = a.Mp / BMP;
+  const int b_begin = (int)(((long long)s * nb) / S);
+  const int b_end = (int)(((long long)(s + 1) * nb) / S);
+  const int nblk = b_end - b_begin;
+
+  // Both roles pass nblk + 2 barriers: one after the first tiles are staged,
+  // then one per step i = 0 .. nblk, in which the dose role evaluates block
+  // b_begin + i (i < nblk) and the back-projection role block b_begin + i - 1
+  // (i > 0).  In step i the dose role stages D of block b + 1 into D buffer
+  // (i + 1) & 1 and the back-projection role D^T of block b into transposed
+  // buffer i & 1, read in step i + 1; phi of block b goes to sPhi[i & 1].
+  // Each buffer written in step i was last read in step i - 1.
+  const u4v* __restrict__ Dg = reinterpret_cast<const u4v*>(a.D);
+  const __bf16* __restrict__ DTg = reinterpret_cast<const __bf16*>(a.DT);
+  if (wave < NG) {
+    u4v pd[NPD];
+    int gpre = 0;
+    // threads past the last chunk load the last one again (every register is
+    // defined on every path) and do not store it
+    auto prefetch_d = [&](int blk) {
+      const u4v* src = Dg + (size_t)blk * NCHD;
+#pragma unroll
+      for (int i = 0; i < NPD; ++i) pd[i] = src[min(tid + NTS * i, NCHD - 1)];
+      if (tid < BMP) gpre = a.grp[blk * BMP + tid];
+    };
+    auto stage_d = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < NPD; ++i) {
+        const int c = tid + NTS * i;
+        if (NCHD % NTS == 0 || c < NCHD) {
+          if constexpr (!FP8) {
+            const int row = c / NC8, c8 = c - row * NC8;
+            *reinterpret_cast<u4v*>(&reinterpret_cast<__bf16*>(sD[buf])[row * DS + 8 * c8]) = pd[i];
+          } else {
+            // (FP8 rows of Kp + 8 bytes are 8-byte aligned)
+            const int row = c / (KP / 16), c16 = c - row * (KP / 16);
+            u2v* dst = reinterpret_cast<u2v*>(&sD[buf][row * DS + 16 * c16]);
+            dst[0] = u2v{pd[i][0], pd[i][1]};
+            dst[1] = u2v{pd[i][2], pd[i][3]};
+          }
+        }
+      }
+      if (tid < BMP) sG[buf][tid] = gpre;
+    };
+
+    op_t tb[2][NK32];
+    float u[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) lp_t_operand<KP, FP8>(a, sPlan[32 * grp + 16 * h + n], q, tb[h], u[h]);
+    double facc[2] = {0.0, 0.0};
+    if (nblk > 0) {
+      prefetch_d(b_begin);
+      stage_d(0);
+      if (nblk > 1) prefetch_d(b_begin + 1);
+    }
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i < nblk) {
+        const int cur = i & 1;
+        const unsigned char* cD = sD[cur];
+        f4v acc[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h][0] = acc[h][1] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < NK32; ++k) {
+          op_t a0, a1;
+          if constexpr (!FP8) {
+            const __bf16* sD16 = reinterpret_cast<const __bf16*>(cD);
+            a0 = *reinterpret_cast<const bf8v*>(&sD16[n * DS + 32 * k + 8 * q]);
+            a1 = *reinterpret_cast<const bf8v*>(&sD16[(16 + n) * DS + 32 * k + 8 * q]);
+          } else {
+            a0 = *reinterpret_cast<const long*>(&cD[n * DS + 32 * k + 8 * q]);
+            a1 = *reinterpret_cast<const long*>(&cD[(16 + n) * DS + 32 * k + 8 * q]);
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            acc[h][0] = LpOp<FP8>::mma(a0, tb[h][k], acc[h][0]);
+            acc[h][1] = LpOp<FP8>::mma(a1, tb[h][k], acc[h][1]);
+          }
+        }
+        bf8v phi[2];
+        lp_epilogue<2, FP8>(acc, u, sG[cur], sP, sW, 32 * grp, lane, phi, facc);
+        sPhi[cur][grp][0][lane] = phi[0];
+        sPhi[cur][grp][1][lane] = phi[1];
+        if (i + 1 < nblk) {
+          stage_d(cur ^ 1);
+          if (i + 2 < nblk) prefetch_d(b_begin + i + 2);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 32 * grp + 16 * h + n;
+      double f = facc[h];
+      f += __shfl_xor(f, 16);
+      f += __shfl_xor(f, 32);
+      if (j0 + col - n < stride && q == 0) a.Fpart[(size_t)s * stride + j0 + col] = f;
+    }
+  } else {
+    const int st = tid - NTS;
+    u4v pt[NPT];
+    auto prefetch_t = [&](int blk) {
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int c = min(st + NTS * i, NCH - 1);
+        const int l = c >> 2, part = c & 3;
+        pt[i] = *reinterpret_cast<const u4v*>(DTg + (size_t)l * a.Mp + (size_t)blk * BMP + part * 8);
+      }
+    };
+    auto stage_t = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int c = st + NTS * i;
+        if (NCH % NTS == 0 || c < NCH) {
+          const int l = c >> 2, part = c & 3;
+          *reinterpret_cast<u4v*>(&sT[buf][l * TS + part * 8]) = pt[i];
+        }
+      }
+    };
+    f4v gacc[2][NK16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < NK16; ++k) gacc[h][k] = f4v{0.f, 0.f, 0.f, 0.f};
+    if (nblk > 0) prefetch_t(b_begin);
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i > 0) {
+        const int prv = (i - 1) & 1;
+        const bf8v phi0 = sPhi[prv][grp][0][lane];
+        const bf8v phi1 = sPhi[prv][grp][1][lane];
+        const __bf16* cT = sT[prv] + n * TS + 8 * q;
+#pragma unroll
+        for (int k = 0; k < NK16; ++k) {
+          const bf8v av = *reinterpret_cast<const bf8v*>(&cT[k * 16 * TS]);
+          gacc[0][k] = mfma_bf16(av, phi0, gacc[0][k]);
+          gacc[1][k] = mfma_bf16(av, phi1, gacc[1][k]);
+        }
+      }
+      if (i < nblk) {
+        stage_t(i & 1);
+        if (i + 1 < nblk) prefetch_t(b_begin + i + 1);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 32 * grp + 16 * h + n;
+      if (j0 + col - n < stride) {  // the same for the whole wavefront
+        float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
+#pragma unroll
+        for (int k = 0; k < NK16; ++k)
+          *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) =
+              make_float4(gacc[h][k][0], gacc[h][k][1], gacc[h][k][2], gacc[h][k][3]);
+      }
     }
   }
 }
@@ -979,24 +1210,28 @@ __global__ __launch_bounds__(64 * NG * NH, (NG * NH == 4) ? 2 : 1) void k_eval_a
 
 template <int KP, int SHAPE>
 __global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_bf16(EvalArgs a) {
-  eval_lp<KP, false, SHAPE>(a, blockIdx.x);
+  if constexpr (SHAPE == 2) eval_lp_ws<KP, false>(a, blockIdx.x);
+  else eval_lp<KP, false, SHAPE>(a, blockIdx.x);
 }
 template <int KP, int SHAPE>
 __global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_bf16_grouped(
     const EvalArgs* __restrict__ args, const int* __restrict__ start, int n) {
   const int c = group_case(start, n, blockIdx.x);
-  eval_lp<KP, false, SHAPE>(args[c], blockIdx.x - start[c]);
+  if constexpr (SHAPE == 2) eval_lp_ws<KP, false>(args[c], blockIdx.x - start[c]);
+  else eval_lp<KP, false, SHAPE>(args[c], blockIdx.x - start[c]);
 }
 
 template <int KP, int SHAPE>
 __global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_fp8(EvalArgs a) {
-  eval_lp<KP, true, SHAPE>(a, blockIdx.x);
+  if constexpr (SHAPE == 2) eval_lp_ws<KP, true>(a, blockIdx.x);
+  else eval_lp<KP, true, SHAPE>(a, blockIdx.x);
 }
 template <int KP, int SHAPE>
 __global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_fp8_grouped(
     const EvalArgs* __restrict__ args, const int* __restrict__ start, int n) {
   const int c = group_case(start, n, blockIdx.x);
-  eval_lp<KP, true, SHAPE>(args[c], blockIdx.x - start[c]);
+  if constexpr (SHAPE == 2) eval_lp_ws<KP, true>(args[c], blockIdx.x - start[c]);
+  else eval_lp<KP, true, SHAPE>(args[c], blockIdx.x - start[c]);
 }
 
 // BF16 / FP8 launch in workgroup shape SHAPE (single case or grouped)
@@ -1019,6 +1254,9 @@ hipError_t launch_lp_shape(int shape, const EvalArgs* single, const EvalArgs* ar
                            int grid, bool fp8, hipStream_t st) {
   if constexpr (lp_shape_ok(KP, 1)) {
     if (shape == 1) return launch_lp<KP, 1>(single, args, start, n, grid, fp8, st);
+  }
+  if constexpr (lp_shape_ok(KP, 2)) {
+    if (shape == 2) return launch_lp<KP, 2>(single, args, start, n, grid, fp8, st);
   }
   if (shape != 0) return hipErrorInvalidValue;
   return launch_lp<KP, 0>(single, args, start, n, grid, fp8, st);

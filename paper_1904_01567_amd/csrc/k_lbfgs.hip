@@ -1,4 +1,4 @@
-// Batched L-BFGS state machine: one wavefront per plan.
+// Batched L-BFGS state machine: one workgroup of two wavefronts per plan.
 //
 // Every round evaluates one point per active plan (k_eval); this kernel then
 // advances each plan by one step of its own sequential algorithm:

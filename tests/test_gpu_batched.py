@@ -26,10 +26,14 @@ def _cases():
             cases.make_case(15, 20, (500, 100, 200, 200), seed=45, jitter=0.2)]
 
 
-def _planners(dtype="f32acc64"):
+def _planners(dtype="f32acc64", lp_shape=None):
     out = []
     for i, c in enumerate(_cases()):
-        out.append(planner(c, cases.hidden_weights(40 + 30 * i, seed=60 + i), dtype=dtype))
+        pl = planner(c, cases.hidden_weights(40 + 30 * i, seed=60 + i), dtype=dtype)
+        if lp_shape is not None:
+            t = pl.tuning()
+            pl.set_tuning(t["split"], lp_shape=lp_shape, xcd_map=t["xcd_map"])
+        out.append(pl)
     return out
 
 
@@ -148,19 +152,21 @@ def test_graph_replays_with_early_exit_match_eager():
         assert x["eval_work"] == y["eval_work"] < x["rounds"]
 
 
-def test_bf16_batched_and_replayed_rounds_match_single_case_runs():
-    # The same three uneven cases in BF16 (workgroups of two plan tiles, a
+@pytest.mark.parametrize("lp_shape", [0, 2])
+def test_bf16_batched_and_replayed_rounds_match_single_case_runs(lp_shape):
+    # The same uneven cases in BF16 (workgroups of two plan tiles, a
     # different dwell count per case) with the stop rule on: lockstep rounds,
-    # plain or replayed from a graph, equal each case run alone bit for bit.
+    # plain or replayed from a graph, equal each case run alone bit for bit,
+    # in the default workgroup shape and in the role-split one.
     # (BF16 line searches stall early, so only the identity is checked.)
     from paper_1904_01567_amd import optimize_many
-    announce("batched vs single, BF16")
-    single = _planners("bf16")
+    announce(f"batched vs single, BF16, workgroup shape {lp_shape}")
+    single = _planners("bf16", lp_shape)
     for pl in single:
         pl.optimize(max_iter=80, eps=1e-4)
     ref = [(pl.weights_x(), pl.metrics()["iterations"]) for pl in single]
     for R in (0, 6):
-        batch = _planners("bf16")
+        batch = _planners("bf16", lp_shape)
         optimize_many(batch, max_iter=80, eps=1e-4, rounds_per_graph=R)
         for k, pl in enumerate(batch):
             np.testing.assert_array_equal(pl.weights_x(), ref[k][0])
@@ -243,12 +249,13 @@ def test_uneven_batch_meets_oracle_optima():
         assert dv.max() <= bench.TOL_V100
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f32acc64"])
+@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32acc64"])
 def test_launch_shapes_give_identical_results(dtype):
     # Every launch shape the autotuner chooses from (split count, tile-to-XCD
-    # mapping, BF16 workgroup of 8 x 16 or 4 x 32 plans, FP64-accumulated
-    # workgroup of 64 or 32 plans) evaluates the same per-plan arithmetic in
-    # the same order: results equal bit for bit.
+    # mapping, BF16 / FP8 workgroup of 8 x 16 or 4 x 32 plans or the
+    # role-split 4 x 32, FP64-accumulated workgroup of 64 or 32 plans)
+    # evaluates the same per-plan arithmetic in the same order: results equal
+    # bit for bit.
     announce(f"launch shapes {dtype}")
     c = cases.case_c1()
     W = cases.hidden_weights(200, seed=71)       # four plan tiles
@@ -257,7 +264,7 @@ def test_launch_shapes_give_identical_results(dtype):
         0.5 + cases.uniform_draws((W.shape[0], c.K), seed=72))
     pl = planner(c, W, dtype=dtype)
     F0, g0 = pl.evaluate(x)
-    shapes = [0, 1]
+    shapes = [0, 1] if dtype == "f32acc64" else [0, 1, 2]
     for shape in shapes:
         for xm in (0, 1):
             for split in (1, 8, 16):
@@ -286,5 +293,6 @@ def test_launch_shapes_give_identical_results(dtype):
             pl.set_tuning(8, lp_shape=1, dtype="f32")
     if dtype == "bf16":
         big = planner(cases.make_case(20, 20, (300, 60, 100, 120), seed=400), W[:8], dtype="bf16")
-        with pytest.raises(GmcoError):  # Kp = 416 has one shape
-            big.set_tuning(4, lp_shape=1)
+        for shape in (1, 2):
+            with pytest.raises(GmcoError):  # Kp = 416 has one shape
+                big.set_tuning(4, lp_shape=shape)
