@@ -218,45 +218,49 @@ __device__ inline void update_plans(const UpdateArgs& a, int p, int round) {
     for (int c = lane; c < kKpMax / 4; c += 64)
       if (c < nq) *reinterpret_cast<float4*>(&sGs[4 * c]) = sum_partials(src + c, stride * Kp / 4, rt.S);
   }
-  __syncthreads();
-  if (wave > 0) return;
+  // Wavefront 0 issues its loads before the barrier, so that they are in
+  // flight while wavefront 1 sums the partials: the plan's vectors, the
+  // stored history pairs in age order (0 = newest before this round; a pair
+  // pushed this round is prepended from registers below, and a push
+  // overwrites the oldest slot only after these loads) and the split
+  // partials of F.
   float xt[E], gt[E], x[E], g[E], d[E];
   float G[E];
-  load_vec(a.xt + row, lane, Kp, xt);
-  load_vec(a.x + row, lane, Kp, x);
-  load_vec(a.g + row, lane, Kp, g);
-  load_vec(a.dir + row, lane, Kp, d);
-
-  // ---- objective and gradient at the evaluated point ----
-  // The stored history pairs in age order (0 = newest before this round),
-  // loaded with the other vectors so that their latency overlaps; a pair
-  // pushed this round is prepended from registers below.  (A push overwrites
-  // the oldest slot only after these loads.)
   const int hc0 = st.hcount;
   float ohs[MH][E], ohy[MH][E];
   double ohr[MH];
-#pragma unroll
-  for (int i = 0; i < MH; ++i) {
-    ohr[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      ohs[i][j] = 0.f;
-      ohy[i][j] = 0.f;
-    }
-    if (i < hc0) {
-      const int slot = (st.hhead - 1 - i + 2 * m) % m;
-      const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
-      const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
-      ohr[i] = a.rho[(size_t)p * m + slot];
-      load_vec(Sd, lane, Kp, ohs[i]);
-      load_vec(Yd, lane, Kp, ohy[i]);
-    }
-  }
-  // gradient of this round's compact column, summed above
-  load_vec_lds(sGs, lane, Kp, G);
-  // split partials of F: one load per lane, then a fixed-order wave sum
   double fpart = 0.0;
-  for (int s = lane; s < rt.S; s += 64) fpart += a.Fpart[s * stride + col];
+  if (wave == 0) {
+    load_vec(a.xt + row, lane, Kp, xt);
+    load_vec(a.x + row, lane, Kp, x);
+    load_vec(a.g + row, lane, Kp, g);
+    load_vec(a.dir + row, lane, Kp, d);
+#pragma unroll
+    for (int i = 0; i < MH; ++i) {
+      ohr[i] = 0.0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        ohs[i][j] = 0.f;
+        ohy[i][j] = 0.f;
+      }
+      if (i < hc0) {
+        const int slot = (st.hhead - 1 - i + 2 * m) % m;
+        const float* Sd = a.Sh + ((size_t)p * m + slot) * Kp;
+        const float* Yd = a.Yh + ((size_t)p * m + slot) * Kp;
+        ohr[i] = a.rho[(size_t)p * m + slot];
+        load_vec(Sd, lane, Kp, ohs[i]);
+        load_vec(Yd, lane, Kp, ohy[i]);
+      }
+    }
+    for (int s = lane; s < rt.S; s += 64) fpart += a.Fpart[s * stride + col];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+
+  // ---- objective and gradient at the evaluated point ----
+  // gradient of this round's compact column, summed above; F from its
+  // split partials in a fixed-order wave sum
+  load_vec_lds(sGs, lane, Kp, G);
   const double Ft = wave_sum(fpart);
 #pragma unroll
   for (int j = 0; j < E; ++j) gt[j] = 4.f * xt[j] * G[j];
