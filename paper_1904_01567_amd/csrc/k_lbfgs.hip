@@ -129,43 +129,50 @@ __device__ inline void store_vec(float* __restrict__ dst, int lane, int Kp, cons
   }
 }
 
-// Sum over the S split-M partials of one float4 of a gradient row, in split
-// order (up to 16 loads in flight); stride4 = float4 between splits.
-__device__ inline float4 sum_partials(const float4* __restrict__ src, size_t stride4, int S) {
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  int s = 0;
-  for (; s + 16 <= S; s += 16) {
-    float4 v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = src[(s + u) * stride4];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      acc.x += v[u].x;
-      acc.y += v[u].y;
-      acc.z += v[u].z;
-      acc.w += v[u].w;
-    }
-  }
-  for (; s + 8 <= S; s += 8) {
-    float4 v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[(s + u) * stride4];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc.x += v[u].x;
-      acc.y += v[u].y;
-      acc.z += v[u].z;
-      acc.w += v[u].w;
-    }
-  }
-  for (; s < S; ++s) {
-    const float4 v = src[s * stride4];
+// Sums over the S split-M partials of up to two float4 of a gradient row
+// (columns c0 and c0 + 64 of the row's float4, the second when two), each in
+// split order, with the loads of both columns in flight together (16 splits
+// at a time); stride4 = float4 between splits.
+__device__ inline void sum_partials2(const float4* __restrict__ src, size_t stride4, int S, bool two,
+                                     float4& acc0, float4& acc1) {
+  acc0 = acc1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto add = [](float4& acc, const float4& v) {
     acc.x += v.x;
     acc.y += v.y;
     acc.z += v.z;
     acc.w += v.w;
+  };
+  int s = 0;
+  for (; s + 16 <= S; s += 16) {
+    float4 v0[16], v1[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      v0[u] = src[(s + u) * stride4];
+      v1[u] = two ? src[(s + u) * stride4 + 64] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      add(acc0, v0[u]);
+      add(acc1, v1[u]);
+    }
   }
-  return acc;
+  for (; s + 8 <= S; s += 8) {
+    float4 v0[8], v1[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v0[u] = src[(s + u) * stride4];
+      v1[u] = two ? src[(s + u) * stride4 + 64] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      add(acc0, v0[u]);
+      add(acc1, v1[u]);
+    }
+  }
+  for (; s < S; ++s) {
+    add(acc0, src[s * stride4]);
+    if (two) add(acc1, src[s * stride4 + 64]);
+  }
 }
 
 template <int E>
@@ -213,10 +220,15 @@ __device__ inline void update_plans(const UpdateArgs& a, int p, int round) {
   const size_t stride = (size_t)rt.ntiles * kPT;
   if (wave == 1) {
     const int nq = Kp / 4;  // float4 of a row (Kp at most 512: two per lane)
-    const float4* src = reinterpret_cast<const float4*>(a.Gpart + col * Kp);
-#pragma unroll
-    for (int c = lane; c < kKpMax / 4; c += 64)
-      if (c < nq) *reinterpret_cast<float4*>(&sGs[4 * c]) = sum_partials(src + c, stride * Kp / 4, rt.S);
+    static_assert(kKpMax / 4 <= 128, "two float4 of a row per lane");
+    if (lane < nq) {
+      const float4* src = reinterpret_cast<const float4*>(a.Gpart + col * Kp) + lane;
+      const bool two = lane + 64 < nq;
+      float4 g0, g1;
+      sum_partials2(src, stride * Kp / 4, rt.S, two, g0, g1);
+      *reinterpret_cast<float4*>(&sGs[4 * lane]) = g0;
+      if (two) *reinterpret_cast<float4*>(&sGs[4 * (lane + 64)]) = g1;
+    }
   }
   // Wavefront 0 issues its loads before the barrier, so that they are in
   // flight while wavefront 1 sums the partials: the plan's vectors, the
