@@ -602,10 +602,11 @@ def main(argv=None) -> int:
     ap.add_argument("--stage-max-ls", type=str, default="30",
                     help="line-search trials per iteration before LS_FAIL, per ladder stage "
                          "(comma list; the last value repeats)")
-    ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1, 2],
+    ap.add_argument("--acc-shape", type=int, default=None, choices=[0, 1, 2, 3],
                     help="workgroup shape of the FP64-accumulated kernel (0: 512 threads per "
                          "64 plans, 1: 256 threads per 32 plans, 2: 1,024 threads per 64 plans "
-                         "in dwell quarters); default: the library's")
+                         "in dwell quarters, 3: 512 threads per 64 plans in two roles); "
+                         "default: the library's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-plans", type=int, default=16,
                     help="plans of the oracle's host timing, spread over the batch")

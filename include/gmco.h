@@ -310,12 +310,15 @@ typedef struct {
   int lp_shape;  /* workgroup shape.  BF16 / FP8: 0 = 8 wavefronts x 16 plans, 1 = 4 x 32
                     (Kp <= 384), 2 = 4 x 32 plans in two roles of 4 wavefronts, dose
                     product with eq. 1 and back-projection of the previous block
-                    (Kp <= 384); all three give the same bits.  FP32 operands with FP64-accumulated dose: 0 = 512
-                    threads per 64-plan tile (dwell halves), 1 = 256 threads per 32
-                    plans (two workgroups per compute unit), 2 = 1,024 threads per
-                    64-plan tile (dwell quarters, four waves per SIMD; Kp a
-                    multiple of 64; the dose partials are added in another
-                    order, an FP64 rounding difference).  Plain FP32: 0 */
+                    (Kp <= 384); all three give the same bits.  FP32 operands with
+                    FP64-accumulated dose: 0 = 512 threads per 64-plan tile (dwell
+                    halves), 1 = 256 threads per 32 plans (two workgroups per
+                    compute unit), 2 = 1,024 threads per 64-plan tile (dwell
+                    quarters, four waves per SIMD; Kp a multiple of 64; the dose
+                    partials are added in another order, an FP64 rounding
+                    difference), 3 = 512 threads per 64-plan tile in two roles
+                    (dose product with eq. 1, back-projection of the previous
+                    block); 0, 1 and 3 give the same bits.  Plain FP32: 0 */
   int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
 } gmco_tuning;
 

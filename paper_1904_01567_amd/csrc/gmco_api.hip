@@ -1148,6 +1148,7 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
   if ((lp && lp_shape_ok(d.Kp, 1)) || dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(1);
   if ((lp && lp_shape_ok(d.Kp, 2)) || (dtype == GMCO_DTYPE_F32_ACC64 && acc_quarters_ok(d.Kp)))
     shapes.push_back(2);
+  if (dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(3);
   int& shape_ref = lp ? d.lp_shape : d.acc_shape;  // (unused by the plain FP32 kernel)
   const int orig_s = S_dense, orig_x = xcd, orig_shape = shape_ref;
   int best = orig_s, best_x = orig_x, best_shape = orig_shape;
@@ -1208,7 +1209,7 @@ int gmco_set_tuning(gmco_ctx* c, int dtype, const gmco_tuning* t) {
   if (t->split < 1 || t->split > d.S_cap || t->split > d.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
   if (t->xcd_map != 0 && t->xcd_map != 1) return fail(c, GMCO_EINVAL, "xcd_map must be 0 or 1");
   const bool acc_ok = dtype == GMCO_DTYPE_F32_ACC64 &&
-                      (t->lp_shape == 1 || (t->lp_shape == 2 && acc_quarters_ok(d.Kp)));
+                      (t->lp_shape == 1 || t->lp_shape == 3 || (t->lp_shape == 2 && acc_quarters_ok(d.Kp)));
   if (lp ? !lp_shape_ok(d.Kp, t->lp_shape) : (t->lp_shape != 0 && !acc_ok))
     return fail(c, GMCO_EINVAL, "workgroup shape not available for this dtype / dwell count");
   (lp ? d.S_lp : d.S) = t->split;

@@ -572,6 +572,191 @@ __device__ inline void eval_acc64(const EvalArgs& a, int bid) {
   }
 }
 
+// Workgroup shape 3: the plan tile of shape 0 (four groups of 16 plans, 512
+// threads) with two roles of four wavefronts instead of dwell halves.  Waves
+// 0-3 run the FP64 dose product of block b over all dwells and eq. 1 for
+// their group and pass phi through LDS; waves 4-7 back-project block b - 1
+// onto all dwells and stage the D tiles.  One wave of each role shares a
+// SIMD, so the conversions, epilogue and staging of one overlap the matrix
+// ops of the other, and no partial dose crosses waves.  Three D buffers and
+// one barrier per block.  The dose keeps shape 0's accumulator chains (four
+// per dwell half, the halves added last) and the objective its row order,
+// so the results are bitwise those of shape 0.
+template <int KP>
+__device__ inline void eval_acc64_ws(const EvalArgs& a, int bid) {
+  constexpr int NG = 4;
+  constexpr int NT = 512;
+  constexpr int NTS = 256;             // threads per role
+  constexpr int NCOL = 16 * NG;
+  constexpr int KS = KP + 16;
+  constexpr int NK = KP / 16;          // 16-dwell slices
+  constexpr int NKH = NK / 2;          // slices of a dwell half
+  static_assert(KP % 32 == 0, "two dwell halves of whole slices");
+  constexpr int NF4 = 4 * KP;          // float4 per 16-point block
+  constexpr int NPF = (NF4 + NTS - 1) / NTS;
+
+  __shared__ __attribute__((aligned(16))) float sD[3][kBM * KS];
+  __shared__ float sPhi[2][NG][4][64];  // phi of a block [buffer][group][r][lane]
+  __shared__ float sW[NCOL * kGmax];
+  __shared__ int sPlan[NCOL];
+  __shared__ int sScan[NT / 64];
+  __shared__ double sP64[kGmax + 1][4];
+  __shared__ int sG[3][kBM];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  const int grp = wave & 3;  // plan group: columns 16 grp .. 16 grp + 15
+  // the last slice holds only padding dwells when Kp - K >= 16: its products
+  // are zero, so both roles skip it
+  const int nk_used = a.last16 ? NK : NK - 1;
+
+  int s, S, stride, j0;
+  if (!tile_setup<NT, NCOL>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
+#pragma unroll
+  for (int j = 0; j <= kGmax; ++j)
+    if (tid == j) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sP64[j][c] = a.gt.prm64[j][c];
+    }
+  const int col = grp * 16 + n;
+  const int b_begin = (int)(((long long)s * a.nblocks) / S);
+  const int b_end = (int)(((long long)(s + 1) * a.nblocks) / S);
+  const int nblk = b_end - b_begin;
+
+  // Both roles pass nblk + 2 barriers: one after the first tile is staged,
+  // then one per step i = 0 .. nblk, in which the dose role evaluates block
+  // b_begin + i (i < nblk, from buffer i % 3) and the back-projection role
+  // block b_begin + i - 1 (i > 0, buffer (i - 1) % 3) and stages block
+  // b_begin + i + 1 into buffer (i + 1) % 3, last read in step i - 1; phi of
+  // block b_begin + i goes to sPhi[i & 1].
+  if (wave < NG) {
+    const int plan = sPlan[col];
+    const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+    const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
+    // t = x^2 of plan n at dwells 16 k + 4 q + j (slice k)
+    float tf[4 * NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const float4 xv = *reinterpret_cast<const float4*>(xrow + 16 * k + 4 * q);
+      tf[4 * k + 0] = pv ? xv.x * xv.x : 0.f;
+      tf[4 * k + 1] = pv ? xv.y * xv.y : 0.f;
+      tf[4 * k + 2] = pv ? xv.z * xv.z : 0.f;
+      tf[4 * k + 3] = pv ? xv.w * xv.w : 0.f;
+    }
+    double facc0 = 0.0, facc1 = 0.0;  // rows 0-1 and 2-3, as the two waves of shape 0
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i < nblk) {
+        const int cur = i % 3;
+        const float* __restrict__ Dc = sD[cur];
+        // t stays FP32 in registers: mark it as changed each block so that
+        // its FP64 conversion is redone per use rather than kept live (in
+        // FP64 it would take 192 registers)
+#pragma unroll
+        for (int j = 0; j < 4 * NK; ++j) asm("" : "+v"(tf[j]));
+        d4v acc[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[h][c] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          if (k == NK - 1 && nk_used < NK) continue;
+          const int h = k / NKH;
+          const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * (q ^ swz_row(n))]);
+          acc[h][0] = mfma_f64(av.x, tf[4 * k + 0], acc[h][0]);
+          acc[h][1] = mfma_f64(av.y, tf[4 * k + 1], acc[h][1]);
+          acc[h][2] = mfma_f64(av.z, tf[4 * k + 2], acc[h][2]);
+          acc[h][3] = mfma_f64(av.w, tf[4 * k + 3], acc[h][3]);
+        }
+        // eq. 1 on the dose of points q + 4 r for plan n
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double d = ((acc[0][0][r] + acc[0][1][r]) + (acc[0][2][r] + acc[0][3][r])) +
+                           ((acc[1][0][r] + acc[1][1][r]) + (acc[1][2][r] + acc[1][3][r]));
+          const int gi = sG[cur][q + 4 * r];
+          const float w = (gi < kGmax) ? sW[col * kGmax + gi] : 0.f;
+          const double lo = fmin(d - sP64[gi][1], 0.0);
+          const double hi = fmax(d - sP64[gi][2], 0.0);
+          const double kap = sP64[gi][0] * lo + sP64[gi][3] * hi;
+          if (r < 2) facc0 += (double)w * (kap * (lo + hi));
+          else facc1 += (double)w * (kap * (lo + hi));
+          sPhi[i & 1][grp][r][lane] = (float)((double)w * kap);
+        }
+      }
+      __syncthreads();
+    }
+    double facc = facc0 + facc1;
+    facc += __shfl_xor(facc, 16);
+    facc += __shfl_xor(facc, 32);
+    if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
+  } else {
+    const int st = tid - NTS;
+    const f4v* __restrict__ Dg = reinterpret_cast<const f4v*>(a.D);
+    f4v pf[NPF];
+    int gpre = 0;
+    // threads past the last chunk load the last one again and do not store it
+    auto prefetch = [&](int blk) {
+      const f4v* src = Dg + (size_t)blk * NF4;
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) pf[i] = src[min(st + NTS * i, NF4 - 1)];
+      if (st < kBM) gpre = a.grp[blk * kBM + st];
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) {
+        const int idx = st + NTS * i;
+        if (NF4 % NTS == 0 || idx < NF4) {
+          const int row = idx / (KP / 4);
+          const int c4 = idx - row * (KP / 4);
+          *reinterpret_cast<f4v*>(&sD[buf][row * KS + 4 * (c4 ^ swz_row(row))]) = pf[i];
+        }
+      }
+      if (st < kBM) sG[buf][st] = gpre;
+    };
+    f4v gacc[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
+    if (nblk > 0) {
+      prefetch(b_begin);
+      stage(0);
+      if (nblk > 1) prefetch(b_begin + 1);
+    }
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i > 0) {
+        const float* __restrict__ Dp = sD[(i - 1) % 3];
+        float phi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) phi[r] = sPhi[(i - 1) & 1][grp][r][lane];
+        // skipped when phi is zero for all 16 points and 16 plans of the group
+        if (wave_any_nonzero(phi)) {
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            if (k == NK - 1 && nk_used < NK) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              gacc[k] = mfma_f32(Dp[(q + 4 * r) * KS + 16 * k + (n ^ (swz_row(q + 4 * r) << 2))], phi[r],
+                                 gacc[k]);
+          }
+        }
+      }
+      if (i + 1 < nblk) {
+        stage((i + 1) % 3);
+        if (i + 2 < nblk) prefetch(b_begin + i + 2);
+      }
+      __syncthreads();
+    }
+    float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) = make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Low-precision operands, FP32 accumulation.
 //   BF16: both products in v_mfma_f32_16x16x32_bf16.
@@ -1207,6 +1392,16 @@ __global__ __launch_bounds__(64 * NG * NH, (NG * NH == 4) ? 2 : 1) void k_eval_a
   const int c = group_case(start, n, blockIdx.x);
   eval_acc64<KP, NG, NH>(args[c], blockIdx.x - start[c]);
 }
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_acc64_ws(EvalArgs a) {
+  eval_acc64_ws<KP>(a, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_acc64_ws_grouped(const EvalArgs* __restrict__ args,
+                                                                   const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_acc64_ws<KP>(args[c], blockIdx.x - start[c]);
+}
 
 template <int KP, int SHAPE>
 __global__ __launch_bounds__(lp_threads(KP, SHAPE), 1) void k_eval_bf16(EvalArgs a) {
@@ -1268,6 +1463,8 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
   const dim3 grid(a.grid), block(256);
   if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 1)
     hipLaunchKernelGGL((k_eval_acc64<KP, 2, 2>), grid, dim3(256), 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 3)
+    hipLaunchKernelGGL((k_eval_acc64_ws<KP>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_ACC64 && a.lp_shape == 2 && acc_quarters_ok(KP))
     hipLaunchKernelGGL((k_eval_acc64<KP, 4, (KP % 64 == 0 ? 4 : 2)>), grid, dim3(KP % 64 == 0 ? 1024 : 512), 0, st,
                        a);
@@ -1290,6 +1487,8 @@ hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int 
   if (grid < 1 || n < 1) return hipErrorInvalidValue;
   if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 1)
     hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 2, 2>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 3)
+    hipLaunchKernelGGL((k_eval_acc64_ws_grouped<KP>), dim3(grid), dim3(512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32_ACC64 && lp_shape == 2 && acc_quarters_ok(KP))
     hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4, (KP % 64 == 0 ? 4 : 2)>), dim3(grid),
                        dim3(KP % 64 == 0 ? 1024 : 512), 0, st, args, start, n);

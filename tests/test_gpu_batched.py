@@ -57,13 +57,16 @@ def test_batched_rounds_match_single_case_runs(per_case):
         announce(f"rounds_per_graph={R}: identical to single-case runs")
 
 
-def test_half_tile_workgroups_match_full_tile_runs():
-    # The FP64-accumulated kernel's 256-thread shape (32 plans per workgroup,
-    # two workgroups per compute unit) computes every plan as the 512-thread
-    # shape does: single-case runs and grouped lockstep rounds, plain or
-    # replayed, equal the full-tile single-case runs bit for bit.
+@pytest.mark.parametrize("shape", [1, 3])
+def test_half_tile_workgroups_match_full_tile_runs(shape):
+    # The FP64-accumulated kernel's 256-thread shape (1: 32 plans per
+    # workgroup, two workgroups per compute unit) and its role-split shape
+    # (3: dose product and back-projection in separate wavefronts) compute
+    # every plan as the 512-thread shape does: single-case runs and grouped
+    # lockstep rounds, plain or replayed, equal the shape-0 single-case runs
+    # bit for bit.
     from paper_1904_01567_amd import optimize_many
-    announce("half-tile FP64-accumulated workgroups")
+    announce(f"FP64-accumulated workgroup shape {shape} against shape 0")
     single = _planners()
     for pl in single:
         pl.optimize(max_iter=60, eps=1e-4)
@@ -72,8 +75,8 @@ def test_half_tile_workgroups_match_full_tile_runs():
     def half(pls):
         for pl in pls:
             t = pl.tuning()
-            pl.set_tuning(t["split"], lp_shape=1, xcd_map=t["xcd_map"])
-            assert pl.tuning()["lp_shape"] == 1
+            pl.set_tuning(t["split"], lp_shape=shape, xcd_map=t["xcd_map"])
+            assert pl.tuning()["lp_shape"] == shape
         return pls
 
     alone = half(_planners())
@@ -253,7 +256,8 @@ def test_uneven_batch_meets_oracle_optima():
 def test_launch_shapes_give_identical_results(dtype):
     # Every launch shape the autotuner chooses from (split count, tile-to-XCD
     # mapping, BF16 / FP8 workgroup of 8 x 16 or 4 x 32 plans or the
-    # role-split 4 x 32, FP64-accumulated workgroup of 64 or 32 plans)
+    # role-split 4 x 32, FP64-accumulated workgroup of 64 or 32 plans or the
+    # role-split 64)
     # evaluates the same per-plan arithmetic in the same order: results equal
     # bit for bit.
     announce(f"launch shapes {dtype}")
@@ -264,7 +268,7 @@ def test_launch_shapes_give_identical_results(dtype):
         0.5 + cases.uniform_draws((W.shape[0], c.K), seed=72))
     pl = planner(c, W, dtype=dtype)
     F0, g0 = pl.evaluate(x)
-    shapes = [0, 1] if dtype == "f32acc64" else [0, 1, 2]
+    shapes = [0, 1, 3] if dtype == "f32acc64" else [0, 1, 2]
     for shape in shapes:
         for xm in (0, 1):
             for split in (1, 8, 16):
