@@ -815,6 +815,7 @@ def main(argv=None) -> int:
                                  for k in range(len(stages))],
             "load_case_once_ms": 1e3 * t_load,
             "acc64_workgroup_shape": pl.tuning("f32acc64")["lp_shape"],
+            "f32_workgroup_shape": pl.tuning("f32")["lp_shape"],
             "lp_workgroup_shape": (pl.tuning(stages[0][0])["lp_shape"]
                                    if stages[0][0] in ("bf16", "fp8") else None),
         },

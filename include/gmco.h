@@ -318,7 +318,9 @@ typedef struct {
                     partials are added in another order, an FP64 rounding
                     difference), 3 = 512 threads per 64-plan tile in two roles
                     (dose product with eq. 1, back-projection of the previous
-                    block); 0, 1 and 3 give the same bits.  Plain FP32: 0 */
+                    block); 0, 1 and 3 give the same bits.  Plain FP32: 0 = 256
+                    threads per 64-plan tile, 3 = 512 threads in the same two roles
+                    (the same bits).  FP32 with FP64-summed chunks: 0 */
   int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
 } gmco_tuning;
 

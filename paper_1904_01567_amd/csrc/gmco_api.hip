@@ -41,7 +41,11 @@ struct Dims {
   int lpt = 1;
   int lp_shape = 0;   // BF16 / FP8 workgroup shape (autotuned)
   int acc_shape = 0;  // FP64-accumulated kernel: 0 = 512 threads per plan tile,
-                      // 1 = 256 threads per half tile (autotuned)
+                      // 1 = 256 threads per half tile, 2 = dwell quarters,
+                      // 3 = two roles (autotuned)
+  int f32_shape = 3;  // plain FP32 kernel: 0 = 256 threads per plan tile,
+                      // 3 = 512 threads in two roles (the default: measured
+                      // faster at the paper-scale case; autotuned)
   int xcd32 = 1;      // XCD-aware tile mapping of the FP32-operand kernels
   int xcd_lp = 1;     // and of the BF16 / FP8 kernels (autotuned)
   int grid_heur = 1;  // largest S * ntiles the per-round heuristic can choose
@@ -177,7 +181,9 @@ Dims make_dims(int M, int K, int Pmax, int n_cu, int Md) {
 // Workgroup shape of the evaluation kernel of `dtype`, and its workgroups
 // per split at the full plan capacity.
 int eval_shape(const Dims& d, int dtype) {
-  return is_low_precision(dtype) ? d.lp_shape : (dtype == GMCO_DTYPE_F32_ACC64 ? d.acc_shape : 0);
+  if (is_low_precision(dtype)) return d.lp_shape;
+  if (dtype == GMCO_DTYPE_F32_ACC64) return d.acc_shape;
+  return dtype == GMCO_DTYPE_F32 ? d.f32_shape : 0;
 }
 int eval_units(const Dims& d, int dtype) {
   if (is_low_precision(dtype)) return (d.ntiles + d.lpt - 1) / d.lpt;
@@ -1148,8 +1154,11 @@ int gmco_autotune(gmco_ctx* c, int dtype, int reps, int* best_split, float* best
   if ((lp && lp_shape_ok(d.Kp, 1)) || dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(1);
   if ((lp && lp_shape_ok(d.Kp, 2)) || (dtype == GMCO_DTYPE_F32_ACC64 && acc_quarters_ok(d.Kp)))
     shapes.push_back(2);
-  if (dtype == GMCO_DTYPE_F32_ACC64) shapes.push_back(3);
-  int& shape_ref = lp ? d.lp_shape : d.acc_shape;  // (unused by the plain FP32 kernel)
+  if (dtype == GMCO_DTYPE_F32_ACC64 || dtype == GMCO_DTYPE_F32) shapes.push_back(3);
+  int chunk_shape = 0;  // the FP32 chunked mode has one shape
+  int& shape_ref = lp ? d.lp_shape
+                      : (dtype == GMCO_DTYPE_F32_ACC64 ? d.acc_shape
+                                                       : (dtype == GMCO_DTYPE_F32 ? d.f32_shape : chunk_shape));
   const int orig_s = S_dense, orig_x = xcd, orig_shape = shape_ref;
   int best = orig_s, best_x = orig_x, best_shape = orig_shape;
   float best_t = 1e30f;
@@ -1208,8 +1217,9 @@ int gmco_set_tuning(gmco_ctx* c, int dtype, const gmco_tuning* t) {
   Dims& d = c->dim;
   if (t->split < 1 || t->split > d.S_cap || t->split > d.nblocks) return fail(c, GMCO_EINVAL, "split out of range");
   if (t->xcd_map != 0 && t->xcd_map != 1) return fail(c, GMCO_EINVAL, "xcd_map must be 0 or 1");
-  const bool acc_ok = dtype == GMCO_DTYPE_F32_ACC64 &&
-                      (t->lp_shape == 1 || t->lp_shape == 3 || (t->lp_shape == 2 && acc_quarters_ok(d.Kp)));
+  const bool acc_ok = (dtype == GMCO_DTYPE_F32_ACC64 &&
+                       (t->lp_shape == 1 || t->lp_shape == 3 || (t->lp_shape == 2 && acc_quarters_ok(d.Kp)))) ||
+                      (dtype == GMCO_DTYPE_F32 && t->lp_shape == 3);
   if (lp ? !lp_shape_ok(d.Kp, t->lp_shape) : (t->lp_shape != 0 && !acc_ok))
     return fail(c, GMCO_EINVAL, "workgroup shape not available for this dtype / dwell count");
   (lp ? d.S_lp : d.S) = t->split;
@@ -1217,6 +1227,7 @@ int gmco_set_tuning(gmco_ctx* c, int dtype, const gmco_tuning* t) {
   (lp ? d.xcd_lp : d.xcd32) = t->xcd_map;
   if (lp) d.lp_shape = t->lp_shape;
   else if (dtype == GMCO_DTYPE_F32_ACC64) d.acc_shape = t->lp_shape;
+  else if (dtype == GMCO_DTYPE_F32) d.f32_shape = t->lp_shape;
   return GMCO_OK;
 }
 

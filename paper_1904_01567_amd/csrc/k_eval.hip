@@ -343,6 +343,164 @@ __device__ inline void eval_f32(const EvalArgs& a, int bid) {
   if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
 }
 
+// Workgroup shape 3 of the FP32 kernel: the 64-plan tile as four groups of
+// 16 plans in two roles of four wavefronts (512 threads, two waves per
+// SIMD).  Waves 0-3 run the dose product of block b over all dwells and eq. 1
+// and pass phi through LDS; waves 4-7 back-project block b - 1 onto all
+// dwells (skipped when phi is zero for the group's 16 points and plans) and
+// stage the D tiles.  The two products take the same matrix time, so each
+// SIMD alternates between equal loads, and the epilogue and staging of one
+// wave overlap the matrix ops of the other.  Three D buffers, one barrier
+// per block; per column the arithmetic and its order are those of shape 0,
+// so the results are bitwise the same.
+template <int KP>
+__device__ inline void eval_f32_ws(const EvalArgs& a, int bid) {
+  constexpr int NG = 4;
+  constexpr int NT = 512;
+  constexpr int NTS = 256;             // threads per role
+  constexpr int KS = KP + 4;           // LDS row stride (as shape 0)
+  constexpr int NK16 = KP / 16;
+  constexpr int NF4 = 4 * KP;          // float4 per 16-point block
+  constexpr int NPF = (NF4 + NTS - 1) / NTS;
+
+  __shared__ __attribute__((aligned(16))) float sD[3][kBM * KS];
+  __shared__ float sPhi[2][NG][4][64];  // phi of a block [buffer][group][r][lane]
+  __shared__ float sW[kPT * kGmax];
+  __shared__ int sPlan[kPT];
+  __shared__ int sScan[NT / 64];
+  __shared__ float4 sP[kGmax + 1];
+  __shared__ int sG[3][kBM];
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wavefront
+  const int lane = tid & 63;
+  const int q = lane >> 4;
+  const int n = lane & 15;
+  const int grp = wave & 3;
+  const int nk_used = a.last16 ? NK16 : NK16 - 1;  // the all-padding slice adds zero products
+
+  int s, S, stride, j0;
+  if (!tile_setup<NT, kPT>(a, bid, sPlan, sScan, sW, s, S, stride, j0)) return;
+#pragma unroll
+  for (int j = 0; j <= kGmax; ++j)
+    if (tid == j) sP[j] = a.gt.prm[j];
+  const int col = grp * 16 + n;
+  const int b_begin = (int)(((long long)s * a.nblocks) / S);
+  const int b_end = (int)(((long long)(s + 1) * a.nblocks) / S);
+  const int nblk = b_end - b_begin;
+
+  // Steps i = 0 .. nblk as in the role-split FP64-accumulated kernel: the
+  // dose role evaluates block b_begin + i from buffer i % 3, the
+  // back-projection role block b_begin + i - 1 from buffer (i - 1) % 3 and
+  // stages block b_begin + i + 1 into buffer (i + 1) % 3.
+  if (wave < NG) {
+    const int plan = sPlan[col];
+    const bool pv = plan >= 0;  // an empty column evaluates t = 0 with zero weights
+    const float* __restrict__ xrow = a.x + (size_t)(pv ? plan : 0) * KP;
+    float tf[KP / 4];
+#pragma unroll
+    for (int k = 0; k < NK16; ++k) {
+      const float4 xv = *reinterpret_cast<const float4*>(xrow + 16 * k + 4 * q);
+      tf[4 * k + 0] = pv ? xv.x * xv.x : 0.f;
+      tf[4 * k + 1] = pv ? xv.y * xv.y : 0.f;
+      tf[4 * k + 2] = pv ? xv.z * xv.z : 0.f;
+      tf[4 * k + 3] = pv ? xv.w * xv.w : 0.f;
+    }
+    double facc = 0.0;
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i < nblk) {
+        const int cur = i % 3;
+        const float* __restrict__ Dc = sD[cur];
+        f4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+        for (int k = 0; k < NK16; ++k) {
+          if (k == NK16 - 1 && nk_used < NK16) continue;
+          const float4 av = *reinterpret_cast<const float4*>(&Dc[n * KS + 16 * k + 4 * q]);
+          acc0 = mfma_f32(av.x, tf[4 * k + 0], acc0);
+          acc1 = mfma_f32(av.y, tf[4 * k + 1], acc1);
+          acc0 = mfma_f32(av.z, tf[4 * k + 2], acc0);
+          acc1 = mfma_f32(av.w, tf[4 * k + 3], acc1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float d = acc0[r] + acc1[r];
+          const int gi = sG[cur][4 * q + r];
+          const float4 pr = sP[gi];
+          const float w = (gi < kGmax) ? sW[col * kGmax + gi] : 0.f;
+          const float lo = fminf(d - pr.y, 0.f);
+          const float hi = fmaxf(d - pr.z, 0.f);
+          const float kap = pr.x * lo + pr.w * hi;
+          facc += (double)(w * (kap * (lo + hi)));
+          sPhi[i & 1][grp][r][lane] = w * kap;
+        }
+      }
+      __syncthreads();
+    }
+    facc += __shfl_xor(facc, 16);
+    facc += __shfl_xor(facc, 32);
+    if (q == 0) a.Fpart[(size_t)s * stride + j0 + col] = facc;
+  } else {
+    const int st = tid - NTS;
+    const f4v* __restrict__ Dg = reinterpret_cast<const f4v*>(a.D);
+    f4v pf[NPF];
+    int gpre = 0;
+    // threads past the last chunk load the last one again and do not store it
+    auto prefetch = [&](int blk) {
+      const f4v* src = Dg + (size_t)blk * NF4;
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) pf[i] = src[min(st + NTS * i, NF4 - 1)];
+      if (st < kBM) gpre = a.grp[blk * kBM + st];
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < NPF; ++i) {
+        const int idx = st + NTS * i;
+        if (NF4 % NTS == 0 || idx < NF4) {
+          const int row = idx / (KP / 4);
+          const int c4 = idx - row * (KP / 4);
+          *reinterpret_cast<f4v*>(&sD[buf][row * KS + 4 * c4]) = pf[i];
+        }
+      }
+      if (st < kBM) sG[buf][st] = gpre;
+    };
+    f4v gacc[NK16];
+#pragma unroll
+    for (int k = 0; k < NK16; ++k) gacc[k] = f4v{0.f, 0.f, 0.f, 0.f};
+    if (nblk > 0) {
+      prefetch(b_begin);
+      stage(0);
+      if (nblk > 1) prefetch(b_begin + 1);
+    }
+    __syncthreads();
+    for (int i = 0; i <= nblk; ++i) {
+      if (i > 0) {
+        const float* __restrict__ Dp = sD[(i - 1) % 3];
+        float phi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) phi[r] = sPhi[(i - 1) & 1][grp][r][lane];
+        if (wave_any_nonzero(phi)) {
+#pragma unroll
+          for (int k = 0; k < NK16; ++k) {
+            if (k == NK16 - 1 && nk_used < NK16) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gacc[k] = mfma_f32(Dp[(4 * q + r) * KS + 16 * k + n], phi[r], gacc[k]);
+          }
+        }
+      }
+      if (i + 1 < nblk) {
+        stage((i + 1) % 3);
+        if (i + 2 < nblk) prefetch(b_begin + i + 2);
+      }
+      __syncthreads();
+    }
+    float* __restrict__ gout = a.Gpart + ((size_t)s * stride + j0 + col) * KP;
+#pragma unroll
+    for (int k = 0; k < NK16; ++k)
+      *reinterpret_cast<float4*>(gout + 16 * k + 4 * q) = make_float4(gacc[k][0], gacc[k][1], gacc[k][2], gacc[k][3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // MODE_ACC64 (FP32 operands, FP64-accumulated dose, FP64 penalty, FP32
 // back-projection), by default with 512 threads: two waves per SIMD.  The
@@ -1381,6 +1539,16 @@ __global__ __launch_bounds__(256, 1) void k_eval_f32_grouped(const EvalArgs* __r
   const int c = group_case(start, n, blockIdx.x);
   eval_f32<KP, MODE>(args[c], blockIdx.x - start[c]);
 }
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_f32_ws(EvalArgs a) {
+  eval_f32_ws<KP>(a, blockIdx.x);
+}
+template <int KP>
+__global__ __launch_bounds__(512, 1) void k_eval_f32_ws_grouped(const EvalArgs* __restrict__ args,
+                                                                 const int* __restrict__ start, int n) {
+  const int c = group_case(start, n, blockIdx.x);
+  eval_f32_ws<KP>(args[c], blockIdx.x - start[c]);
+}
 
 template <int KP, int NG, int NH>
 __global__ __launch_bounds__(64 * NG * NH, (NG * NH == 4) ? 2 : 1) void k_eval_acc64(EvalArgs a) {
@@ -1472,6 +1640,8 @@ hipError_t launch_kp(const EvalArgs& a, int dtype, hipStream_t st) {
     hipLaunchKernelGGL((k_eval_acc64<KP, 4, 2>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_CHUNK64>), grid, block, 0, st, a);
+  else if (dtype == GMCO_DTYPE_F32 && a.lp_shape == 3)
+    hipLaunchKernelGGL((k_eval_f32_ws<KP>), grid, dim3(512), 0, st, a);
   else if (dtype == GMCO_DTYPE_F32)
     hipLaunchKernelGGL((k_eval_f32<KP, MODE_F32>), grid, block, 0, st, a);
   else if (dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8)
@@ -1496,6 +1666,8 @@ hipError_t launch_kp_grouped(const EvalArgs* args, const int* start, int n, int 
     hipLaunchKernelGGL((k_eval_acc64_grouped<KP, 4, 2>), dim3(grid), dim3(512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32_CHUNK64)
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_CHUNK64>), dim3(grid), dim3(256), 0, st, args, start, n);
+  else if (dtype == GMCO_DTYPE_F32 && lp_shape == 3)
+    hipLaunchKernelGGL((k_eval_f32_ws_grouped<KP>), dim3(grid), dim3(512), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_F32)
     hipLaunchKernelGGL((k_eval_f32_grouped<KP, MODE_F32>), dim3(grid), dim3(256), 0, st, args, start, n);
   else if (dtype == GMCO_DTYPE_BF16 || dtype == GMCO_DTYPE_FP8)

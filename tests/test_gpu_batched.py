@@ -57,17 +57,17 @@ def test_batched_rounds_match_single_case_runs(per_case):
         announce(f"rounds_per_graph={R}: identical to single-case runs")
 
 
-@pytest.mark.parametrize("shape", [1, 3])
-def test_half_tile_workgroups_match_full_tile_runs(shape):
+@pytest.mark.parametrize("dtype,shape", [("f32acc64", 1), ("f32acc64", 3), ("f32", 3)])
+def test_half_tile_workgroups_match_full_tile_runs(dtype, shape):
     # The FP64-accumulated kernel's 256-thread shape (1: 32 plans per
     # workgroup, two workgroups per compute unit) and its role-split shape
-    # (3: dose product and back-projection in separate wavefronts) compute
-    # every plan as the 512-thread shape does: single-case runs and grouped
-    # lockstep rounds, plain or replayed, equal the shape-0 single-case runs
-    # bit for bit.
+    # (3: dose product and back-projection in separate wavefronts), and the
+    # plain FP32 kernel's role-split shape 3, compute every plan as shape 0
+    # does: single-case runs and grouped lockstep rounds, plain or replayed,
+    # equal the shape-0 single-case runs bit for bit.
     from paper_1904_01567_amd import optimize_many
-    announce(f"FP64-accumulated workgroup shape {shape} against shape 0")
-    single = _planners()
+    announce(f"{dtype} workgroup shape {shape} against shape 0")
+    single = _planners(dtype)
     for pl in single:
         pl.optimize(max_iter=60, eps=1e-4)
     ref = [(pl.weights_x(), pl.metrics()["iterations"]) for pl in single]
@@ -79,13 +79,13 @@ def test_half_tile_workgroups_match_full_tile_runs(shape):
             assert pl.tuning()["lp_shape"] == shape
         return pls
 
-    alone = half(_planners())
+    alone = half(_planners(dtype))
     for pl, (x, it) in zip(alone, ref):
         pl.optimize(max_iter=60, eps=1e-4)
         np.testing.assert_array_equal(pl.weights_x(), x)
         np.testing.assert_array_equal(pl.metrics()["iterations"], it)
     for R in (0, 6):
-        batch = half(_planners())
+        batch = half(_planners(dtype))
         optimize_many(batch, max_iter=60, eps=1e-4, rounds_per_graph=R)
         for pl, (x, it) in zip(batch, ref):
             np.testing.assert_array_equal(pl.weights_x(), x)
@@ -252,12 +252,12 @@ def test_uneven_batch_meets_oracle_optima():
         assert dv.max() <= bench.TOL_V100
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32acc64"])
+@pytest.mark.parametrize("dtype", ["bf16", "fp8", "f32acc64", "f32"])
 def test_launch_shapes_give_identical_results(dtype):
     # Every launch shape the autotuner chooses from (split count, tile-to-XCD
     # mapping, BF16 / FP8 workgroup of 8 x 16 or 4 x 32 plans or the
     # role-split 4 x 32, FP64-accumulated workgroup of 64 or 32 plans or the
-    # role-split 64)
+    # role-split 64, plain FP32 workgroup of 64 plans in one or two roles)
     # evaluates the same per-plan arithmetic in the same order: results equal
     # bit for bit.
     announce(f"launch shapes {dtype}")
@@ -268,7 +268,7 @@ def test_launch_shapes_give_identical_results(dtype):
         0.5 + cases.uniform_draws((W.shape[0], c.K), seed=72))
     pl = planner(c, W, dtype=dtype)
     F0, g0 = pl.evaluate(x)
-    shapes = [0, 1, 3] if dtype == "f32acc64" else [0, 1, 2]
+    shapes = {"f32acc64": [0, 1, 3], "f32": [0, 3]}.get(dtype, [0, 1, 2])
     for shape in shapes:
         for xm in (0, 1):
             for split in (1, 8, 16):
@@ -293,8 +293,9 @@ def test_launch_shapes_give_identical_results(dtype):
     assert t["split"] == best and t["tuned"] == 1
     from paper_1904_01567_amd import GmcoError
     if dtype == "f32acc64":
-        with pytest.raises(GmcoError):  # the plain FP32 kernel has one shape
-            pl.set_tuning(8, lp_shape=1, dtype="f32")
+        for shape in (1, 2):
+            with pytest.raises(GmcoError):  # the plain FP32 kernel has shapes 0 and 3
+                pl.set_tuning(8, lp_shape=shape, dtype="f32")
     if dtype == "bf16":
         big = planner(cases.make_case(20, 20, (300, 60, 100, 120), seed=400), W[:8], dtype="bf16")
         for shape in (1, 2):
