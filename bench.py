@@ -59,8 +59,8 @@ EVAL_KERNEL = {"f32acc64": "k_eval_acc64", "f32": "k_eval_f32", "f32chunk64": "k
 # (KiB per dispatch, median of the full-batch dispatches) scaled by the same
 # counters on a 256 MiB copy (read x 2.000, write x 1.000); valid only for the
 # kernel code they were taken on (kernel_source_hash: comments left out).
-EVAL_TRAFFIC = {"k_eval_sha256": "261774a6cf8e0c65", "dtype": "f32acc64", "plans": 1000,
-                "fetch_kib": 21271.9, "fetch_scale": 262144.0 / 131092.1,
+EVAL_TRAFFIC = {"k_eval_sha256": "eb5d295c832319da", "dtype": "f32acc64", "plans": 1000,
+                "fetch_kib": 21271.9, "fetch_scale": 262144.0 / 131093.0,
                 "write_kib": 24708.0, "write_scale": 262144.0 / 262144.0}
 ITERS = {"f32acc64": 2000, "f32chunk64": 2000, "f32": 2000}
 # MI355X dense peaks (TFLOP/s): FP64 matrix 78.6, FP32 matrix 157.3.
