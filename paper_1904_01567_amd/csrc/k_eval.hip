@@ -10,7 +10,11 @@
 // (eq. 2).  The dose tile never leaves the chip: each block of D (16 points
 // for FP32 operands, 32 for BF16 / FP8) is staged once in LDS and feeds both
 // products, and the dwell times and gradient accumulators of each wave's
-// plans stay in registers for the whole point range.
+// plans stay in registers for the whole point range.  Each operand type has
+// a role-split workgroup shape besides its default one: some waves run the
+// dose product with eq. 1 of block b, the others back-project block b - 1
+// and stage the tiles, so that one's epilogue and staging overlap the
+// other's matrix ops (the default for FP32 and BF16 operands).
 //
 // Operand layout of the 16x16x4 matrix ops for lane l (q = l / 16, n = l % 16):
 // A[n][q], B[q][n].  Accumulator register r holds C[4 q + r][n] for the FP32
