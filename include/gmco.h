@@ -290,17 +290,17 @@ int gmco_optimize_many(gmco_ctx* const* ctxs, int n, const gmco_run* run, gmco_r
  * candidate launch shape and keep the fastest: the split count of the point
  * range (workgroups per plan tile of 64 plans, or per pair of tiles for the
  * BF16 and FP8 kernels up to 448 padded dwells; up to 32), the tile-to-XCD
- * mapping (all tiles of one point range on one XCD, or round-robin) and, for
- * BF16 / FP8 up to 384 padded dwells, the workgroup shape (eight wavefronts
- * of 16 plans, two per SIMD, or four of 32 plans, one per SIMD).  reps timed
+ * mapping (all tiles of one point range on one XCD, or round-robin) and the
+ * workgroup shape of dtype's kernel (gmco_tuning.lp_shape lists them).  reps timed
  * launches per candidate on the context stream.  Needs a weight batch.
  * best_split / best_us may be NULL.  The tuning belongs to the kernel family
  * of dtype (FP32 operands, or BF16 / FP8); the split is used by its rounds in
  * which every plan tile of the batch capacity is active (rounds with fewer
  * active plans, stopped plans being compacted out, choose their split on the
  * device to fill the compute units), the mapping and shape by every round.
- * No choice changes a result: the per-plan arithmetic and its order are the
- * same in every shape. */
+ * No choice changes a result, except the FP64-accumulated dwell-quarter
+ * shape (an FP64 rounding difference): the per-plan arithmetic and its order
+ * are the same in every other shape. */
 int gmco_autotune(gmco_ctx* ctx, int dtype, int reps, int* best_split, float* best_us);
 
 /* The launch shape of a kernel family (see gmco_autotune). */
@@ -328,8 +328,8 @@ typedef struct {
  * dtype), e.g. to reuse an autotuned shape on cases of the same size.  Needs
  * a loaded case.  set: EINVAL for a split outside 1..the autotuner's range,
  * xcd_map not 0/1 or a shape not available for dtype at the case's dwell
- * count.  The FP32-operand kernels share split and mapping; the shape is
- * the FP64-accumulated kernel's. */
+ * count.  The FP32-operand kernels (plain FP32 and FP64-accumulated) share
+ * split and mapping and have a workgroup shape each. */
 int gmco_get_tuning(const gmco_ctx* ctx, int dtype, gmco_tuning* out);
 int gmco_set_tuning(gmco_ctx* ctx, int dtype, const gmco_tuning* t);
 
