@@ -320,7 +320,9 @@ typedef struct {
                     (dose product with eq. 1, back-projection of the previous
                     block); 0, 1 and 3 give the same bits.  Plain FP32: 0 = 256
                     threads per 64-plan tile, 3 = 512 threads in the same two roles
-                    (the same bits).  FP32 with FP64-summed chunks: 0 */
+                    (the same bits).  FP32 with FP64-summed chunks: 0.  Defaults
+                    after gmco_load_case: BF16 2 (up to 384 padded dwells), FP8 0,
+                    FP32 3, FP64-accumulated 0 (3 from 448 padded dwells) */
   int xcd_map;   /* 1: tiles of one point range on one XCD when the grid allows */
 } gmco_tuning;
 

@@ -542,6 +542,10 @@ int gmco_load_case(gmco_ctx* c, const gmco_case* cs) {
   // BF16: the role-split workgroup where it exists (measured faster at the
   // paper-scale case; FP8 keeps shape 0, which measured as fast)
   if (c->dtype == GMCO_DTYPE_BF16 && lp_shape_ok(d.Kp, 2)) c->dim.lp_shape = 2;
+  // FP64-accumulated dose from 448 padded dwells: the role-split workgroup,
+  // which needs no register spill there (shape 0 spills; 655 against 784 us
+  // per full evaluation measured at 512 dwells; shape 0 stays ahead at 416)
+  if (d.Kp >= 448) c->dim.acc_shape = 3;
   c->lay = L;
   c->G = G;
   c->O = O;
