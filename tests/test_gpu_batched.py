@@ -301,3 +301,22 @@ def test_launch_shapes_give_identical_results(dtype):
         for shape in (1, 2):
             with pytest.raises(GmcoError):  # Kp = 416 has one shape
                 big.set_tuning(4, lp_shape=shape)
+
+
+def test_default_workgroup_shapes():
+    # After a case is loaded each kernel family starts in the shape measured
+    # fastest at the paper-scale case: BF16 role-split up to 384 padded
+    # dwells, FP32 role-split, FP64-accumulated shape 0 below 448 padded
+    # dwells and role-split from there (where shape 0 spills registers).
+    announce("default workgroup shapes")
+    c = cases.case_c1()
+    W = cases.hidden_weights(64, seed=90)
+    bf = planner(c, W, dtype="bf16")
+    assert bf.tuning("bf16")["lp_shape"] == 2
+    assert bf.tuning("f32")["lp_shape"] == 3
+    assert bf.tuning("f32acc64")["lp_shape"] == 0
+    big = planner(cases.make_case(20, 23, (300, 60, 100, 120), seed=401), W[:8], dtype="f32acc64")
+    assert big.tuning()["lp_shape"] == 3  # 460 dwells: Kp = 480
+    small = planner(cases.make_case(20, 20, (300, 60, 100, 120), seed=400), W[:8], dtype="bf16")
+    assert small.tuning()["lp_shape"] == 0  # 400 dwells: Kp = 416, one BF16 shape
+    assert small.tuning("f32acc64")["lp_shape"] == 0
