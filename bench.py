@@ -617,6 +617,9 @@ def main(argv=None) -> int:
                          "points, semi-axes +-20 %%) of --plans plans each in lockstep rounds "
                          "replayed from a captured HIP graph, splits autotuned per shape")
     ap.add_argument("--rounds-per-graph", type=int, default=16)
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune every ladder stage's launch shape once after loading the case "
+                         "(outside the timed steps); default: the library's shapes")
     ap.add_argument("--tuning-cache", type=str, default=None,
                     help="--batched: reuse autotuned launch shapes per (kernel family, padded dwells, "
                          "point bucket, plans) from this JSON file, and add new ones to it")
@@ -716,6 +719,10 @@ def main(argv=None) -> int:
     if args.acc_shape is not None:
         t = pl.tuning("f32acc64")
         pl.set_tuning(t["split"], lp_shape=args.acc_shape, xcd_map=t["xcd_map"], dtype="f32acc64")
+    if args.autotune:
+        pl.set_weights(W)
+        for dt in dict.fromkeys(d for d, _ in stages):
+            pl.autotune(dtype=dt, reps=10)
 
     if args.calibrate:
         # the run's stages from the start, the last one capped at n accepted
@@ -816,6 +823,8 @@ def main(argv=None) -> int:
             "load_case_once_ms": 1e3 * t_load,
             "acc64_workgroup_shape": pl.tuning("f32acc64")["lp_shape"],
             "f32_workgroup_shape": pl.tuning("f32")["lp_shape"],
+            "tuning": ({d: pl.tuning(d) for d in dict.fromkeys(d for d, _ in stages)}
+                       if args.autotune else "library defaults"),
             "lp_workgroup_shape": (pl.tuning(stages[0][0])["lp_shape"]
                                    if stages[0][0] in ("bf16", "fp8") else None),
         },
